@@ -1,0 +1,226 @@
+/*
+ * bddmp: BDD-based min-marginal averaging for 0-1 ILP relaxations on one
+ * MI355X (gfx950) GPU.
+ *
+ * The method is dual block coordinate ascent on the Lagrangean decomposition
+ * of a 0-1 ILP into one binary decision diagram (BDD) per linear row
+ * (J.-H. Lange and P. Swoboda, "Efficient Message Passing for 0-1 ILPs with
+ * Binary Decision Diagrams", ICML 2021):
+ *   - problem: min c^T x s.t. each row sum_i a_ji x_i (=, <=, >=) b_j,
+ *     x in {0,1}^n (Sec. 3, Def. "Binary program", Example "ILP");
+ *   - dual (D): max sum_j E^j(lambda^j), E^j = min over the row's feasible set
+ *     of x^T lambda^j, s.t. sum_{j in J_i} lambda^j_i = c_i (Sec. 3.1);
+ *   - one iteration = a forward and a backward pass of Alg. "Min-marginal
+ *     averaging" (Sec. 3.2) with the incremental BDD updates of Sec. 5.3-5.4;
+ *   - outputs: the bound, multipliers, min-marginals (eq. "min-marginals")
+ *     and the rounded primal of eq. "preferred-variable-value" (Sec. 4).
+ *
+ * Conventions for every entry point:
+ *   - Return value: BDDMP_OK (0) or a negative status below; after a failure
+ *     bddmp_last_error() returns a message (thread-local).
+ *   - Host input arrays are copied; the caller keeps ownership.
+ *   - Handles are created and destroyed only through this API. A plan must
+ *     outlive every solver bound from it.
+ *   - Device memory belongs to the caller. bddmp_solver_bind receives one
+ *     arena (at least bddmp_stats.device_bytes bytes, 256-byte aligned) and
+ *     the library keeps all of its device state there; it allocates no other
+ *     device memory and never frees the arena.
+ *   - Device work is enqueued on the caller's HIP stream. Only the calls that
+ *     hand back host values (lower_bound, lb_history, round_primal,
+ *     time_kernels) synchronise that stream.
+ *   - One handle is used by one host thread at a time.
+ *   - Per-incidence arrays use the canonical incidence order: rows in input
+ *     order, and within a row its variables in processing order (the levels
+ *     of its BDD). Per-node arrays use rows, then levels, then the in-level
+ *     node order (breadth-first from the root, 0-arc child first).
+ */
+#ifndef BDDMP_H
+#define BDDMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BDDMP_OK 0
+#define BDDMP_INVALID_ARG (-1)    /* bad pointer, size, index, sense or permutation          */
+#define BDDMP_ROW_INFEASIBLE (-2) /* a row has no 0/1 solution (its BDD would be empty)      */
+#define BDDMP_BDD_TOO_LARGE (-3)  /* node budget exceeded, or a level wider than 32767       */
+#define BDDMP_NOT_INTEGER (-4)    /* reserved: coefficients arrive as integers               */
+#define BDDMP_CONFLICT (-5)       /* rows force one variable to both 0 and 1                 */
+#define BDDMP_DEVICE (-6)         /* a HIP call failed; the message holds HIP's error string */
+#define BDDMP_BAD_STATE (-7)      /* call out of order                                       */
+#define BDDMP_NONFINITE (-8)      /* NaN or infinite multiplier or bound                     */
+
+/* row senses */
+#define BDDMP_EQ 0
+#define BDDMP_LE 1
+#define BDDMP_GE 2
+
+typedef struct bddmp_problem bddmp_problem; /* host: costs, rows, order              */
+typedef struct bddmp_plan bddmp_plan;       /* host: BDDs, wave schedule, HBM layout */
+typedef struct bddmp_solver bddmp_solver;   /* device state in the caller's arena    */
+
+typedef struct {
+  int32_t order_mode;     /* 0: the problem's order (identity if none set); 1: greedy colouring */
+  int32_t hist_cap;       /* bound history ring length on the device (default 4096)           */
+  int64_t node_budget;    /* max total BDD nodes, 0 = unlimited                                */
+  double stop_rel_impr;   /* reserved (iteration counts are explicit), 0                        */
+  float alpha;            /* reserved for the smoothed variant, 0 = min-plus                    */
+  int32_t reserved;
+  const char *tiling;     /* reserved, may be NULL                                              */
+} bddmp_options;
+
+typedef struct {
+  int64_t n_vars, n_bdds, n_nodes, n_arcs_live, n_arcs_bot, n_incidences;
+  int32_t waves_fwd, waves_bwd; /* dependency waves per forward / backward pass            */
+  int64_t device_bytes;         /* arena size bddmp_solver_bind needs                      */
+  int32_t max_width;            /* widest BDD level                                        */
+  int32_t n_shapes;             /* distinct BDD shapes built (rows sharing coefficients)   */
+  int32_t max_rows_per_var;     /* max |J_i|                                               */
+  int32_t bwd_contiguous;       /* 1 if every backward wave is a contiguous layer range    */
+  int64_t fwd_tiles, bwd_tiles; /* workgroups per forward / backward pass                  */
+} bddmp_stats;
+
+typedef struct {
+  double fwd_ms, bwd_ms, lb_ms;          /* summed kernel time per class over the timed iterations */
+  int64_t fwd_launches, bwd_launches, lb_launches;
+  double fwd_bytes, bwd_bytes;           /* algorithmic bytes moved by all launches of the class   */
+  double iter_ms;                        /* event time per iteration without per-launch events     */
+} bddmp_kernel_times;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t bddmp_version(void);
+
+/* Message of the calling thread's last failure ("" if none). Valid until the next call. */
+const char *bddmp_last_error(void);
+
+/* Fills *opt with defaults (order_mode 0, hist_cap 4096, no budget). */
+int32_t bddmp_options_default(bddmp_options *opt);
+
+/*
+ * A problem with n_vars binary variables and objective c (Sec. 3, eq. "binary-program").
+ * cost: host array [n_vars], copied. n_vars >= 0.
+ */
+int32_t bddmp_problem_create(int32_t n_vars, const double *cost, bddmp_problem **out);
+
+/*
+ * Appends n_rows linear rows sum_q coef[q] x_{col[q]} (sense) rhs for q in
+ * [row_ptr[r], row_ptr[r+1]) (CSR; row_ptr has n_rows+1 entries, row_ptr[0] may be nonzero).
+ * Each row becomes one subproblem X_j with I_j = {i : a_ji != 0} (Sec. 3, Example "ILP");
+ * zero coefficients are dropped. A column repeated inside a row is INVALID_ARG.
+ * sense: BDDMP_EQ, BDDMP_LE or BDDMP_GE. All arrays are host memory and copied.
+ */
+int32_t bddmp_problem_add_rows(bddmp_problem *p, int32_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                               const int64_t *coef, const int8_t *sense, const int64_t *rhs);
+
+/*
+ * Processing order of Alg. "Min-marginal averaging": perm[r] is the variable processed r-th by
+ * the forward pass (the backward pass uses the reverse). perm: host [n_vars], a permutation;
+ * NULL restores the identity.
+ */
+int32_t bddmp_problem_set_order(bddmp_problem *p, const int32_t *perm);
+
+/*
+ * Host build: one canonical quasi-reduced BDD per row (Sec. 5.1 Def. "Binary decision diagram",
+ * Prop. "Canonicity"; threshold construction of Sec. 5.2 in O(N log W)), the variable->row
+ * incidence J_i (Sec. 3.1), the dependency waves that run Alg. "Min-marginal averaging" exactly
+ * (a variable's wave is one more than the latest wave of its predecessor in any of its rows), and
+ * the level-sorted structure-of-arrays layout for HBM. opt may be NULL (defaults).
+ * Errors: ROW_INFEASIBLE, BDD_TOO_LARGE, CONFLICT (a variable forced to 0 by one row and to 1
+ * by another), INVALID_ARG.
+ */
+int32_t bddmp_plan_create(const bddmp_problem *p, const bddmp_options *opt, bddmp_plan **out);
+
+/* Sizes of the plan (host). */
+int32_t bddmp_plan_stats(const bddmp_plan *plan, bddmp_stats *out);
+
+/* The processing order the plan uses: perm_out host [n_vars]. */
+int32_t bddmp_plan_export_order(const bddmp_plan *plan, int32_t *perm_out);
+
+/*
+ * Canonical structure for exact comparisons: level_width and level_var host [n_incidences],
+ * lo and hi host [n_nodes] holding in-level child indices of the next level, -1 for the false
+ * terminal and -2 for the true terminal. Any pointer may be NULL.
+ */
+int32_t bddmp_plan_export_structure(const bddmp_plan *plan, int32_t *level_width, int32_t *level_var,
+                                    int32_t *lo, int32_t *hi);
+
+/* Forward and backward wave of every variable (1-based, 0 for variables in no row); host [n_vars]. */
+int32_t bddmp_plan_export_waves(const bddmp_plan *plan, int32_t *wave_fwd, int32_t *wave_bwd);
+
+/*
+ * Binds a plan to caller device memory and a stream: uploads the layout into dev_arena
+ * (device pointer, >= device_bytes, 256-byte aligned), sets lambda^j_i = c_i/|J_i| and runs the
+ * initial backward sweep that fills every backward message (Alg. "Min-marginal averaging"
+ * initialisation; Prop. "correctness"), then records LB_0. hip_stream is a hipStream_t (NULL =
+ * the null stream). Asynchronous on that stream.
+ */
+int32_t bddmp_solver_bind(const bddmp_plan *plan, void *dev_arena, size_t bytes, void *hip_stream,
+                          bddmp_solver **out);
+
+/*
+ * Restarts the method on the bound data without uploading again: lambda^j_i = c_i/|J_i|, the
+ * initial backward sweep, and LB_0 appended to the bound history. Asynchronous.
+ */
+int32_t bddmp_solver_reset(bddmp_solver *s);
+
+/*
+ * n_iters iterations (forward pass then backward pass, Sec. 3.2 with Sec. 5.4), each followed by
+ * the fp64 bound LB_t = sum_j E^j (+ sum of min(0, c_i) over variables in no row), appended to the
+ * device bound history. Asynchronous.
+ */
+int32_t bddmp_solver_iterate(bddmp_solver *s, int32_t n_iters);
+
+/*
+ * Latest bound, dual-feasibility residual max_i |c_i - sum_j lambda^j_i| and the bound valid
+ * for any lambda, LB + sum_i min(0, c_i - sum_j lambda^j_i) (App. A.1). Synchronises the stream.
+ * Any output pointer may be NULL. NONFINITE if the bound is NaN.
+ */
+int32_t bddmp_solver_lower_bound(bddmp_solver *s, double *lb, double *residual, double *any_lambda_bound);
+
+/* Copies the last min(cap, recorded) bounds (oldest first) to lb_host; *n_out = count. Synchronises. */
+int32_t bddmp_solver_lb_history(bddmp_solver *s, double *lb_host, int32_t cap, int32_t *n_out);
+
+/*
+ * Fresh min-marginals at the current multipliers (eq. "min-marginals" via eqs. "arc-marginal" and
+ * "marginal-aggregation"): a forward sweep without updates, then the level minima.
+ * m0_dev, m1_dev: device [n_incidences] in canonical order (either may be NULL). Asynchronous.
+ */
+int32_t bddmp_solver_min_marginals(bddmp_solver *s, float *m0_dev, float *m1_dev);
+
+/* Multipliers lambda^j_i to lam_dev (device [n_incidences], canonical order). Asynchronous. */
+int32_t bddmp_solver_get_lambda(bddmp_solver *s, float *lam_dev);
+
+/* Replaces the multipliers from lam_dev (device, canonical order) and re-runs the initial
+ * backward sweep (resume from a checkpoint); appends the new bound. Asynchronous. */
+int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
+
+/*
+ * Rounded primal from fresh min-marginals (Sec. 4): M_i = sum_j (m1_ij - m0_ij) in ascending row
+ * order, x_i = [M_i <= 0] (eq. "preferred-variable-value"); variables in no row take [c_i < 0].
+ * x_host: host [n_vars]; M_dev: device [n_vars] or NULL; obj: c^T x in fp64; n_violated: rows
+ * the point violates (each row's BDD path decides). Synchronises.
+ */
+int32_t bddmp_solver_round_primal(bddmp_solver *s, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated);
+
+/*
+ * Diagnostics: runs n_iters iterations with a HIP event pair around every wave launch and reports
+ * summed kernel times per class with the algorithmic bytes of those launches (forward and backward
+ * passes move 20 bytes per node and 8 per incidence: arcs 8, messages 12, multiplier 8), then the
+ * same number of iterations without per-launch events for iter_ms. The solver advances by
+ * 2*n_iters iterations. Synchronises.
+ */
+int32_t bddmp_solver_time_kernels(bddmp_solver *s, int32_t n_iters, bddmp_kernel_times *out);
+
+void bddmp_solver_destroy(bddmp_solver *s);
+void bddmp_plan_destroy(bddmp_plan *plan);
+void bddmp_problem_destroy(bddmp_problem *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDDMP_H */

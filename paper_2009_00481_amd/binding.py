@@ -1,0 +1,373 @@
+"""Thin Python binding of the bddmp C-ABI (``include/bddmp.h``).
+
+Functions carry the C names and only marshal arguments: every step of the
+method runs inside ``libbddmp.so`` (host builder and planner, HIP kernels).
+PyTorch supplies device memory (the solver arena, output tensors) and the
+stream. There is no fallback: if the library is missing, loading fails loudly.
+
+``Problem``, ``Plan`` and ``Solver`` are small owners of the handles on top of
+those functions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbddmp.so")
+
+BDDMP_OK = 0
+STATUS = {-1: "INVALID_ARG", -2: "ROW_INFEASIBLE", -3: "BDD_TOO_LARGE", -4: "NOT_INTEGER", -5: "CONFLICT",
+          -6: "DEVICE", -7: "BAD_STATE", -8: "NONFINITE"}
+
+
+class BddmpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bddmp {STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("order_mode", C.c_int32), ("hist_cap", C.c_int32), ("node_budget", C.c_int64),
+                ("stop_rel_impr", C.c_double), ("alpha", C.c_float), ("reserved", C.c_int32),
+                ("tiling", C.c_char_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_vars", C.c_int64), ("n_bdds", C.c_int64), ("n_nodes", C.c_int64), ("n_arcs_live", C.c_int64),
+                ("n_arcs_bot", C.c_int64), ("n_incidences", C.c_int64), ("waves_fwd", C.c_int32),
+                ("waves_bwd", C.c_int32), ("device_bytes", C.c_int64), ("max_width", C.c_int32),
+                ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
+                ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("fwd_ms", C.c_double), ("bwd_ms", C.c_double), ("lb_ms", C.c_double),
+                ("fwd_launches", C.c_int64), ("bwd_launches", C.c_int64), ("lb_launches", C.c_int64),
+                ("fwd_bytes", C.c_double), ("bwd_bytes", C.c_double), ("iter_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol the header declares, with (restype, argtypes)
+_P, _I32, _I64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+SIGNATURES = {
+    "bddmp_version": (_I32, []),
+    "bddmp_last_error": (C.c_char_p, []),
+    "bddmp_options_default": (_I32, [C.POINTER(Options)]),
+    "bddmp_problem_create": (_I32, [_I32, _P, C.POINTER(_P)]),
+    "bddmp_problem_add_rows": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
+    "bddmp_problem_set_order": (_I32, [_P, _P]),
+    "bddmp_plan_create": (_I32, [_P, C.POINTER(Options), C.POINTER(_P)]),
+    "bddmp_plan_stats": (_I32, [_P, C.POINTER(Stats)]),
+    "bddmp_plan_export_order": (_I32, [_P, _P]),
+    "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
+    "bddmp_plan_export_waves": (_I32, [_P, _P, _P]),
+    "bddmp_solver_bind": (_I32, [_P, _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "bddmp_solver_reset": (_I32, [_P]),
+    "bddmp_solver_iterate": (_I32, [_P, _I32]),
+    "bddmp_solver_lower_bound": (_I32, [_P, C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
+    "bddmp_solver_lb_history": (_I32, [_P, _P, _I32, C.POINTER(_I32)]),
+    "bddmp_solver_min_marginals": (_I32, [_P, _P, _P]),
+    "bddmp_solver_get_lambda": (_I32, [_P, _P]),
+    "bddmp_solver_set_lambda": (_I32, [_P, _P]),
+    "bddmp_solver_round_primal": (_I32, [_P, _P, _P, C.POINTER(_D), C.POINTER(_I64)]),
+    "bddmp_solver_time_kernels": (_I32, [_P, _I32, C.POINTER(KernelTimes)]),
+    "bddmp_solver_destroy": (None, [_P]),
+    "bddmp_plan_destroy": (None, [_P]),
+    "bddmp_problem_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libbddmp.so (built in-tree by ``paper_2009_00481_amd/build.py``); raise if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2009_00481_amd/build.py "
+                              "(the HIP library has no fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != BDDMP_OK:
+        raise BddmpError(rc, lib().bddmp_last_error().decode())
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------------------
+# C entry points, same names
+# ---------------------------------------------------------------------------
+
+def bddmp_version() -> int:
+    return int(lib().bddmp_version())
+
+
+def bddmp_options_default() -> Options:
+    o = Options()
+    _check(lib().bddmp_options_default(C.byref(o)))
+    return o
+
+
+def bddmp_problem_create(n_vars: int, cost) -> C.c_void_p:
+    cost = np.ascontiguousarray(cost, np.float64)
+    assert cost.shape == (n_vars,)
+    h = C.c_void_p()
+    _check(lib().bddmp_problem_create(int(n_vars), _ptr(cost), C.byref(h)))
+    return h
+
+
+def bddmp_problem_add_rows(h, row_ptr, col, coef, sense, rhs):
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    coef = np.ascontiguousarray(coef, np.int64)
+    sense = np.ascontiguousarray(sense, np.int8)
+    rhs = np.ascontiguousarray(rhs, np.int64)
+    n_rows = int(row_ptr.shape[0] - 1)
+    _check(lib().bddmp_problem_add_rows(h, n_rows, _ptr(row_ptr), _ptr(col) if col.size else None,
+                                        _ptr(coef) if coef.size else None, _ptr(sense), _ptr(rhs)))
+
+
+def bddmp_problem_set_order(h, perm):
+    if perm is None:
+        _check(lib().bddmp_problem_set_order(h, None))
+        return
+    perm = np.ascontiguousarray(perm, np.int32)
+    _check(lib().bddmp_problem_set_order(h, _ptr(perm)))
+
+
+def bddmp_plan_create(problem, options: Options | None = None):
+    h = C.c_void_p()
+    _check(lib().bddmp_plan_create(problem, C.byref(options) if options is not None else None, C.byref(h)))
+    return h
+
+
+def bddmp_plan_stats(plan) -> Stats:
+    s = Stats()
+    _check(lib().bddmp_plan_stats(plan, C.byref(s)))
+    return s
+
+
+def bddmp_plan_export_order(plan, n: int):
+    out = np.zeros(max(n, 1), np.int32)
+    _check(lib().bddmp_plan_export_order(plan, _ptr(out)))
+    return out[:n]
+
+
+def bddmp_plan_export_structure(plan, n_incidences: int, n_nodes: int):
+    w = np.zeros(max(n_incidences, 1), np.int32)
+    v = np.zeros(max(n_incidences, 1), np.int32)
+    lo = np.zeros(max(n_nodes, 1), np.int32)
+    hi = np.zeros(max(n_nodes, 1), np.int32)
+    _check(lib().bddmp_plan_export_structure(plan, _ptr(w), _ptr(v), _ptr(lo), _ptr(hi)))
+    return w[:n_incidences], v[:n_incidences], lo[:n_nodes], hi[:n_nodes]
+
+
+def bddmp_plan_export_waves(plan, n: int):
+    f = np.zeros(max(n, 1), np.int32)
+    b = np.zeros(max(n, 1), np.int32)
+    _check(lib().bddmp_plan_export_waves(plan, _ptr(f), _ptr(b)))
+    return f[:n], b[:n]
+
+
+def bddmp_solver_bind(plan, arena, nbytes: int, stream):
+    h = C.c_void_p()
+    _check(lib().bddmp_solver_bind(plan, _dptr(arena), C.c_size_t(int(nbytes)), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def bddmp_solver_reset(h):
+    _check(lib().bddmp_solver_reset(h))
+
+
+def bddmp_solver_iterate(h, n_iters: int):
+    _check(lib().bddmp_solver_iterate(h, int(n_iters)))
+
+
+def bddmp_solver_lower_bound(h):
+    lb, r, b = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().bddmp_solver_lower_bound(h, C.byref(lb), C.byref(r), C.byref(b)))
+    return lb.value, r.value, b.value
+
+
+def bddmp_solver_lb_history(h, cap: int):
+    out = np.zeros(max(cap, 1), np.float64)
+    n = C.c_int32()
+    _check(lib().bddmp_solver_lb_history(h, _ptr(out), int(cap), C.byref(n)))
+    return out[: n.value]
+
+
+def bddmp_solver_min_marginals(h, m0, m1):
+    _check(lib().bddmp_solver_min_marginals(h, _dptr(m0), _dptr(m1)))
+
+
+def bddmp_solver_get_lambda(h, lam):
+    _check(lib().bddmp_solver_get_lambda(h, _dptr(lam)))
+
+
+def bddmp_solver_set_lambda(h, lam):
+    _check(lib().bddmp_solver_set_lambda(h, _dptr(lam)))
+
+
+def bddmp_solver_round_primal(h, M, n: int):
+    x = np.zeros(max(n, 1), np.int8)
+    obj = C.c_double()
+    nv = C.c_int64()
+    _check(lib().bddmp_solver_round_primal(h, _dptr(M), _ptr(x), C.byref(obj), C.byref(nv)))
+    return x[:n], obj.value, nv.value
+
+
+def bddmp_solver_time_kernels(h, n_iters: int) -> KernelTimes:
+    t = KernelTimes()
+    _check(lib().bddmp_solver_time_kernels(h, int(n_iters), C.byref(t)))
+    return t
+
+
+def bddmp_solver_destroy(h):
+    lib().bddmp_solver_destroy(h)
+
+
+def bddmp_plan_destroy(h):
+    lib().bddmp_plan_destroy(h)
+
+
+def bddmp_problem_destroy(h):
+    lib().bddmp_problem_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# owners
+# ---------------------------------------------------------------------------
+
+class Problem:
+    def __init__(self, n_vars: int, cost):
+        self.n = int(n_vars)
+        self.h = bddmp_problem_create(self.n, cost)
+
+    @classmethod
+    def from_ilp(cls, ilp, order=True) -> "Problem":
+        p = cls(ilp.n, ilp.cost)
+        bddmp_problem_add_rows(p.h, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs)
+        if order and ilp.order is not None:
+            bddmp_problem_set_order(p.h, ilp.order)
+        return p
+
+    def add_rows(self, row_ptr, col, coef, sense, rhs):
+        bddmp_problem_add_rows(self.h, row_ptr, col, coef, sense, rhs)
+
+    def set_order(self, perm):
+        bddmp_problem_set_order(self.h, perm)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            bddmp_problem_destroy(self.h)
+            self.h = None
+
+
+class Plan:
+    def __init__(self, problem: Problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096):
+        o = bddmp_options_default()
+        o.order_mode = order_mode
+        o.node_budget = node_budget
+        o.hist_cap = hist_cap
+        self.n = problem.n
+        self.h = bddmp_plan_create(problem.h, o)
+        self.stats = bddmp_plan_stats(self.h)
+
+    def order(self):
+        return bddmp_plan_export_order(self.h, self.n)
+
+    def structure(self):
+        return bddmp_plan_export_structure(self.h, self.stats.n_incidences, self.stats.n_nodes)
+
+    def waves(self):
+        return bddmp_plan_export_waves(self.h, self.n)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            bddmp_plan_destroy(self.h)
+            self.h = None
+
+
+class Solver:
+    """Device solver: the arena is a torch uint8 tensor on ``device``; work runs on ``stream``."""
+
+    def __init__(self, plan: Plan, device="cuda", stream=None):
+        import torch
+
+        self.plan = plan
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = int(plan.stats.device_bytes)
+        self.arena = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.h = bddmp_solver_bind(plan.h, self.arena, nbytes, self.stream.cuda_stream)
+
+    @property
+    def n_incidences(self):
+        return int(self.plan.stats.n_incidences)
+
+    def reset(self):
+        bddmp_solver_reset(self.h)
+
+    def iterate(self, n_iters: int):
+        bddmp_solver_iterate(self.h, n_iters)
+
+    def lower_bound(self):
+        return bddmp_solver_lower_bound(self.h)
+
+    def lb_history(self, cap: int = 1 << 16):
+        return bddmp_solver_lb_history(self.h, cap)
+
+    def min_marginals(self):
+        I = self.n_incidences
+        m0 = self.torch.empty(max(I, 1), dtype=self.torch.float32, device=self.device)
+        m1 = self.torch.empty(max(I, 1), dtype=self.torch.float32, device=self.device)
+        bddmp_solver_min_marginals(self.h, m0, m1)
+        return m0[:I], m1[:I]
+
+    def get_lambda(self):
+        I = self.n_incidences
+        lam = self.torch.empty(max(I, 1), dtype=self.torch.float32, device=self.device)
+        bddmp_solver_get_lambda(self.h, lam)
+        return lam[:I]
+
+    def set_lambda(self, lam):
+        assert lam.dtype == self.torch.float32 and lam.is_contiguous() and lam.numel() == self.n_incidences
+        bddmp_solver_set_lambda(self.h, lam)
+
+    def round_primal(self):
+        n = self.plan.n
+        M = self.torch.empty(max(n, 1), dtype=self.torch.float32, device=self.device)
+        x, obj, nv = bddmp_solver_round_primal(self.h, M, n)
+        return M[:n], x, obj, nv
+
+    def time_kernels(self, n_iters: int) -> dict:
+        return bddmp_solver_time_kernels(self.h, n_iters).as_dict()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            bddmp_solver_destroy(self.h)
+            self.h = None

@@ -1,0 +1,271 @@
+// C-ABI of bddmp: argument checks, handle ownership, status codes and the last-error message.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "bddmp.h"
+#include "internal.h"
+#include "solver.h"
+
+struct bddmp_problem {
+  bddmp::Problem p;
+};
+struct bddmp_plan {
+  bddmp::Plan plan;
+};
+struct bddmp_solver {
+  bddmp::Solver *s = nullptr;
+};
+
+namespace bddmp {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int32_t set_error(int32_t code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+}  // namespace bddmp
+
+using bddmp::set_error;
+
+namespace {
+
+template <class F>
+int32_t guarded(F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return set_error(BDDMP_INVALID_ARG, "host allocation failed");
+  } catch (const std::exception &e) {
+    return set_error(BDDMP_INVALID_ARG, std::string("exception: ") + e.what());
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bddmp_version(void) { return 10000; }
+
+const char *bddmp_last_error(void) { return bddmp::g_last_error.c_str(); }
+
+int32_t bddmp_options_default(bddmp_options *opt) {
+  if (!opt) return set_error(BDDMP_INVALID_ARG, "null options");
+  std::memset(opt, 0, sizeof *opt);
+  opt->hist_cap = 4096;
+  return BDDMP_OK;
+}
+
+int32_t bddmp_problem_create(int32_t n_vars, const double *cost, bddmp_problem **out) {
+  return guarded([&] {
+    if (!out) return set_error(BDDMP_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (n_vars < 0 || (n_vars > 0 && !cost)) return set_error(BDDMP_INVALID_ARG, "bad n_vars or null cost");
+    auto *h = new bddmp_problem();
+    h->p.n = n_vars;
+    h->p.cost.assign(cost, cost + n_vars);
+    *out = h;
+    return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_problem_add_rows(bddmp_problem *h, int32_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                               const int64_t *coef, const int8_t *sense, const int64_t *rhs) {
+  return guarded([&] {
+    if (!h || n_rows < 0) return set_error(BDDMP_INVALID_ARG, "null problem or negative row count");
+    if (n_rows == 0) return int32_t(BDDMP_OK);
+    if (!row_ptr || !sense || !rhs) return set_error(BDDMP_INVALID_ARG, "null row array");
+    bddmp::Problem &p = h->p;
+    const int64_t base = row_ptr[0];
+    for (int32_t r = 0; r < n_rows; ++r)
+      if (row_ptr[r + 1] < row_ptr[r]) return set_error(BDDMP_INVALID_ARG, "row_ptr not non-decreasing");
+    const int64_t nnz = row_ptr[n_rows] - base;
+    if (nnz > 0 && (!col || !coef)) return set_error(BDDMP_INVALID_ARG, "null col or coef");
+    for (int64_t q = 0; q < nnz; ++q)
+      if (col[base + q] < 0 || col[base + q] >= p.n) return set_error(BDDMP_INVALID_ARG, "column out of range");
+    for (int32_t r = 0; r < n_rows; ++r)
+      if (sense[r] < 0 || sense[r] > 2) return set_error(BDDMP_INVALID_ARG, "sense must be 0, 1 or 2");
+    const int64_t off = p.row_ptr.back();
+    for (int32_t r = 0; r < n_rows; ++r) p.row_ptr.push_back(off + row_ptr[r + 1] - base);
+    p.col.insert(p.col.end(), col + base, col + base + nnz);
+    p.coef.insert(p.coef.end(), coef + base, coef + base + nnz);
+    p.sense.insert(p.sense.end(), sense, sense + n_rows);
+    p.rhs.insert(p.rhs.end(), rhs, rhs + n_rows);
+    return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_problem_set_order(bddmp_problem *h, const int32_t *perm) {
+  return guarded([&] {
+    if (!h) return set_error(BDDMP_INVALID_ARG, "null problem");
+    bddmp::Problem &p = h->p;
+    if (!perm) {
+      p.order.clear();
+      return int32_t(BDDMP_OK);
+    }
+    std::vector<char> seen(size_t(p.n), 0);
+    for (int32_t r = 0; r < p.n; ++r) {
+      if (perm[r] < 0 || perm[r] >= p.n || seen[perm[r]]) return set_error(BDDMP_INVALID_ARG, "order is not a permutation");
+      seen[perm[r]] = 1;
+    }
+    p.order.assign(perm, perm + p.n);
+    return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_plan_create(const bddmp_problem *h, const bddmp_options *opt, bddmp_plan **out) {
+  return guarded([&] {
+    if (!h || !out) return set_error(BDDMP_INVALID_ARG, "null problem or out");
+    *out = nullptr;
+    bddmp_options o;
+    if (opt) o = *opt;
+    else bddmp_options_default(&o);
+    auto *pl = new bddmp_plan();
+    const int32_t rc = bddmp::make_plan(h->p, o, pl->plan);
+    if (rc != BDDMP_OK) {
+      delete pl;
+      return rc;
+    }
+    *out = pl;
+    return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
+  if (!h || !out) return set_error(BDDMP_INVALID_ARG, "null plan or out");
+  const bddmp::Plan &P = h->plan;
+  std::memset(out, 0, sizeof *out);
+  out->n_vars = P.n;
+  out->n_bdds = P.m;
+  out->n_nodes = P.N;
+  out->n_arcs_live = P.live;
+  out->n_arcs_bot = P.bot;
+  out->n_incidences = P.I;
+  out->waves_fwd = P.Df;
+  out->waves_bwd = P.Db;
+  out->device_bytes = int64_t(P.lay.total);
+  out->max_width = P.max_width;
+  out->n_shapes = int32_t(P.shapes.size());
+  out->max_rows_per_var = P.max_j;
+  out->bwd_contiguous = P.bwd_contiguous ? 1 : 0;
+  out->fwd_tiles = int64_t(P.fwd_tiles.size() / 2 + P.fwd_big.size() / 2);
+  out->bwd_tiles = int64_t(P.bwd_tiles.size() / 2 + P.bwd_big.size() / 2);
+  return BDDMP_OK;
+}
+
+int32_t bddmp_plan_export_order(const bddmp_plan *h, int32_t *perm_out) {
+  if (!h || (!perm_out && h->plan.n)) return set_error(BDDMP_INVALID_ARG, "null plan or output");
+  std::memcpy(perm_out, h->plan.order.data(), sizeof(int32_t) * size_t(h->plan.n));
+  return BDDMP_OK;
+}
+
+int32_t bddmp_plan_export_structure(const bddmp_plan *h, int32_t *level_width, int32_t *level_var, int32_t *lo,
+                                    int32_t *hi) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  const bddmp::Plan &P = h->plan;
+  int64_t qi = 0, qn = 0;
+  for (int32_t j = 0; j < P.m; ++j) {
+    if (P.row_shape[j] < 0) continue;
+    const bddmp::Shape &sh = P.shapes[P.row_shape[j]];
+    for (int32_t l = 0; l < sh.k; ++l, ++qi) {
+      if (level_width) level_width[qi] = sh.first[l + 1] - sh.first[l];
+      if (level_var) level_var[qi] = P.inc_var[qi];
+    }
+    for (size_t u = 0; u < sh.lo.size(); ++u, ++qn) {
+      if (lo) lo[qn] = sh.lo[u];
+      if (hi) hi[qn] = sh.hi[u];
+    }
+  }
+  return BDDMP_OK;
+}
+
+int32_t bddmp_plan_export_waves(const bddmp_plan *h, int32_t *wave_fwd, int32_t *wave_bwd) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  const bddmp::Plan &P = h->plan;
+  if (wave_fwd) std::memcpy(wave_fwd, P.wave_f.data(), sizeof(int32_t) * size_t(P.n));
+  if (wave_bwd) std::memcpy(wave_bwd, P.wave_b.data(), sizeof(int32_t) * size_t(P.n));
+  return BDDMP_OK;
+}
+
+int32_t bddmp_solver_bind(const bddmp_plan *h, void *dev_arena, size_t bytes, void *hip_stream, bddmp_solver **out) {
+  return guarded([&] {
+    if (!h || !out) return set_error(BDDMP_INVALID_ARG, "null plan or out");
+    *out = nullptr;
+    bddmp::Solver *s = nullptr;
+    const int32_t rc = bddmp::solver_bind(h->plan, dev_arena, bytes, hip_stream, s);
+    if (rc != BDDMP_OK) return rc;
+    auto *w = new bddmp_solver();
+    w->s = s;
+    *out = w;
+    return int32_t(BDDMP_OK);
+  });
+}
+
+#define SOLVER_OR_FAIL(h)                                                   \
+  if (!(h) || !(h)->s) return set_error(BDDMP_BAD_STATE, "null or unbound solver")
+
+int32_t bddmp_solver_reset(bddmp_solver *h) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_reset(*h->s); });
+}
+
+int32_t bddmp_solver_iterate(bddmp_solver *h, int32_t n_iters) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_iterate(*h->s, n_iters); });
+}
+
+int32_t bddmp_solver_lower_bound(bddmp_solver *h, double *lb, double *residual, double *any_lambda_bound) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_lower_bound(*h->s, lb, residual, any_lambda_bound); });
+}
+
+int32_t bddmp_solver_lb_history(bddmp_solver *h, double *lb_host, int32_t cap, int32_t *n_out) {
+  SOLVER_OR_FAIL(h);
+  if (cap < 0 || (cap > 0 && !lb_host)) return set_error(BDDMP_INVALID_ARG, "bad history buffer");
+  return guarded([&] { return bddmp::solver_lb_history(*h->s, lb_host, cap, n_out); });
+}
+
+int32_t bddmp_solver_min_marginals(bddmp_solver *h, float *m0_dev, float *m1_dev) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_min_marginals(*h->s, m0_dev, m1_dev); });
+}
+
+int32_t bddmp_solver_get_lambda(bddmp_solver *h, float *lam_dev) {
+  SOLVER_OR_FAIL(h);
+  if (!lam_dev) return set_error(BDDMP_INVALID_ARG, "null output");
+  return guarded([&] { return bddmp::solver_get_lambda(*h->s, lam_dev); });
+}
+
+int32_t bddmp_solver_set_lambda(bddmp_solver *h, const float *lam_dev) {
+  SOLVER_OR_FAIL(h);
+  if (!lam_dev) return set_error(BDDMP_INVALID_ARG, "null input");
+  return guarded([&] { return bddmp::solver_set_lambda(*h->s, lam_dev); });
+}
+
+int32_t bddmp_solver_round_primal(bddmp_solver *h, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_round_primal(*h->s, M_dev, x_host, obj, n_violated); });
+}
+
+int32_t bddmp_solver_time_kernels(bddmp_solver *h, int32_t n_iters, bddmp_kernel_times *out) {
+  SOLVER_OR_FAIL(h);
+  if (!out || n_iters < 0) return set_error(BDDMP_INVALID_ARG, "bad arguments");
+  return guarded([&] { return bddmp::solver_time_kernels(*h->s, n_iters, out); });
+}
+
+void bddmp_solver_destroy(bddmp_solver *h) {
+  if (!h) return;
+  bddmp::solver_destroy(h->s);
+  delete h;
+}
+
+void bddmp_plan_destroy(bddmp_plan *h) { delete h; }
+
+void bddmp_problem_destroy(bddmp_problem *h) { delete h; }
+
+}  // extern "C"

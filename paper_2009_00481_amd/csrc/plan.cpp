@@ -1,0 +1,456 @@
+// Planner: rows -> BDD shapes, incidence J_i, dependency waves and the HBM layout.
+//
+// Waves. Alg. "Min-marginal averaging" visits variables one at a time in the processing order.
+// Visiting i touches, in each row j of J_i, only level l_j(i): the forward step there reads the
+// forward messages of level l-1 and lambda^j of the previous variable of row j, the min-marginals
+// read the backward messages of level l+1, and the update couples the rows of J_i through their
+// sum. So i may run as soon as the previous variable of each of its rows has run:
+//   wave_f(i) = 1 + max_j wave_f(prev_j(i))   (0 if i opens all its rows),
+// and the backward pass mirrors this with the next variable of each row. Variables of one wave
+// share no row, and every value a variable reads was written in an earlier wave, so running the
+// waves in order performs the sequential algorithm's arithmetic exactly (the argument of the
+// proof of Prop. "correctness", applied to all rows at once).
+//
+// Layout. Layers (one per incidence = one BDD level) are stored forward-wave-major: by forward
+// wave, then by the variable's processing rank, then ascending row. A variable's layers are
+// therefore one contiguous segment, and each wave is one contiguous layer range. Node arrays
+// follow the layer order. Arcs are packed as two 16-bit child codes per node.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace bddmp {
+
+void greedy_colour_order(const Problem &p, std::vector<int32_t> &order) {
+  const int32_t n = p.n;
+  const int64_t m = int64_t(p.row_ptr.size()) - 1;
+  std::vector<int64_t> vptr(size_t(n) + 1, 0);
+  for (int32_t c : p.col) vptr[c + 1]++;
+  for (int32_t i = 0; i < n; ++i) vptr[i + 1] += vptr[i];
+  std::vector<int64_t> vrows(p.col.size());
+  std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+  for (int64_t j = 0; j < m; ++j)
+    for (int64_t q = p.row_ptr[j]; q < p.row_ptr[j + 1]; ++q) vrows[fill[p.col[q]]++] = j;
+  std::vector<int32_t> colour(size_t(n), -1);
+  std::vector<int32_t> mark;
+  int32_t ncol = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    for (int64_t q = vptr[v]; q < vptr[v + 1]; ++q) {
+      const int64_t j = vrows[q];
+      for (int64_t t = p.row_ptr[j]; t < p.row_ptr[j + 1]; ++t) {
+        const int32_t cu = colour[p.col[t]];
+        if (cu >= 0) {
+          if (cu >= int32_t(mark.size())) mark.resize(size_t(cu) + 1, -1);
+          mark[cu] = v;
+        }
+      }
+    }
+    int32_t c = 0;
+    while (c < int32_t(mark.size()) && mark[c] == v) ++c;
+    colour[v] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  order.resize(size_t(n));
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return colour[x] < colour[y]; });
+}
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile;
+// a variable with more rows than kTile gets a big tile of its own. Tiles are (start, end) pairs.
+void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj, int64_t pos0,
+               std::vector<int32_t> &tiles, std::vector<int32_t> &big, WaveRange &wr) {
+  wr.tile_begin = int32_t(tiles.size() / 2);
+  wr.big_begin = int32_t(big.size() / 2);
+  int64_t pos = pos0, start = pos0;
+  int32_t cnt = 0;
+  for (int32_t i : vars) {
+    const int32_t c = nj[i];
+    if (c > kTile) {
+      if (cnt) { tiles.push_back(int32_t(start)); tiles.push_back(int32_t(pos)); }
+      big.push_back(int32_t(pos));
+      big.push_back(int32_t(pos + c));
+      pos += c;
+      start = pos;
+      cnt = 0;
+      continue;
+    }
+    if (cnt + c > kTile) {
+      tiles.push_back(int32_t(start));
+      tiles.push_back(int32_t(pos));
+      start = pos;
+      cnt = 0;
+    }
+    pos += c;
+    cnt += c;
+  }
+  if (cnt) { tiles.push_back(int32_t(start)); tiles.push_back(int32_t(pos)); }
+  wr.tile_end = int32_t(tiles.size() / 2);
+  wr.big_end = int32_t(big.size() / 2);
+}
+
+// Checks every index the wave, bound and output kernels read or write against the array it
+// addresses, and that tiles hold whole variable segments. Returns an empty string when sound.
+std::string validate_layout(const Plan &P) {
+  const int64_t I = P.I, N = P.N;
+  if (int64_t(P.node_off.size()) != I + 1 || P.node_off[0] != 0 || P.node_off[I] != N) return "node_off";
+  for (int64_t L = 0; L < I; ++L) {
+    const int32_t no = P.node_off[L], w = P.node_off[L + 1] - no;
+    if (w <= 0 || w > kMaxWidth) return "layer width";
+    const int32_t co = P.child_off[L];
+    int32_t wc = 0;
+    if (co >= 0) {
+      const int32_t c = P.canon_of[L];
+      const int32_t Lc = P.layer_of[c + 1];
+      if (co != P.node_off[Lc]) return "child_off";
+      wc = P.node_off[Lc + 1] - co;
+    }
+    for (int32_t u = 0; u < w; ++u) {
+      const uint32_t a = P.arcs[no + u];
+      for (uint32_t ch : {a & 0xFFFFu, a >> 16}) {
+        if (ch == kBot) continue;
+        if (ch == kTop) {
+          if (co >= 0) return "TOP before the last level";
+          continue;
+        }
+        if (co < 0 || int32_t(ch) >= wc) return "child index outside the next level";
+      }
+    }
+    const uint32_t pos = P.seg[L] & 0xFFFFu, len = P.seg[L] >> 16;
+    if (len == 0 || pos >= len || int32_t(len) != P.var_nj[P.layer_var[L]]) return "segment";
+    if (P.layer_of[P.canon_of[L]] != L) return "canon_of / layer_of";
+  }
+  auto check_tiles = [&](const std::vector<int32_t> &tiles, const std::vector<WaveRange> &waves, bool fwd,
+                         bool big) -> std::string {
+    for (const WaveRange &wr : waves) {
+      const int32_t b0 = big ? wr.big_begin : wr.tile_begin, b1 = big ? wr.big_end : wr.tile_end;
+      for (int32_t t = b0; t < b1; ++t) {
+        const int64_t p0 = tiles[2 * size_t(t)], p1 = tiles[2 * size_t(t) + 1];
+        const int64_t cap = big ? kBigMax : kTile;
+        if (p1 <= p0 || p1 - p0 > cap || p0 < 0 || p1 > I) return "tile bounds";
+        auto layer = [&](int64_t p) -> int64_t { return (!fwd && wr.list) ? P.bwd_list[size_t(p)] : p; };
+        const int64_t Lf = layer(p0), Ll = layer(p1 - 1);
+        if (Lf < 0 || Lf >= I || Ll < 0 || Ll >= I) return "tile layer";
+        if ((P.seg[Lf] & 0xFFFFu) != 0) return "tile starts inside a segment";
+        if ((P.seg[Ll] & 0xFFFFu) != (P.seg[Ll] >> 16) - 1) return "tile ends inside a segment";
+        if (big && (P.seg[Lf] >> 16) != uint32_t(p1 - p0)) return "big tile is not one variable";
+      }
+    }
+    return "";
+  };
+  for (auto r : {check_tiles(P.fwd_tiles, P.fwd_waves, true, false), check_tiles(P.fwd_big, P.fwd_waves, true, true),
+                 check_tiles(P.bwd_tiles, P.bwd_waves, false, false), check_tiles(P.bwd_big, P.bwd_waves, false, true)})
+    if (!r.empty()) return r;
+  // every layer is visited exactly once per pass, in a position whose segment slot matches
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<uint8_t> seen(size_t(I), 0);
+    const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+    for (const WaveRange &wr : waves)
+      for (int big = 0; big < 2; ++big) {
+        const auto &tiles = pass ? (big ? P.bwd_big : P.bwd_tiles) : (big ? P.fwd_big : P.fwd_tiles);
+        for (int32_t t = big ? wr.big_begin : wr.tile_begin; t < (big ? wr.big_end : wr.tile_end); ++t)
+          for (int64_t p = tiles[2 * size_t(t)]; p < tiles[2 * size_t(t) + 1]; ++p) {
+            const int64_t L = (pass && wr.list) ? P.bwd_list[size_t(p)] : p;
+            if (seen[L]++) return "layer visited twice in a pass";
+            const int64_t head = p - int64_t(P.seg[L] & 0xFFFFu);
+            if (head < tiles[2 * size_t(t)] || head + int64_t(P.seg[L] >> 16) > tiles[2 * size_t(t) + 1])
+              return "segment leaves its tile";
+          }
+      }
+    for (int64_t L = 0; L < I; ++L)
+      if (!seen[L]) return "layer missing from a pass";
+  }
+  for (int32_t j = 0; j < P.m; ++j)
+    if (P.root_node[j] >= N || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
+  for (int32_t i = 0; i < P.n; ++i)
+    if (P.var_nj[i] && (P.var_first[i] < 0 || P.var_first[i] + P.var_nj[i] > I)) return "var_first";
+  return "";
+}
+
+}  // namespace
+
+int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
+  P = Plan{};
+  const int32_t n = p.n;
+  const int64_t m64 = int64_t(p.row_ptr.size()) - 1;
+  if (m64 > INT32_MAX - 1) return set_error(BDDMP_INVALID_ARG, "too many rows");
+  const int32_t m = int32_t(m64);
+  P.n = n;
+  P.m = m;
+  P.hist_cap = opt.hist_cap > 0 ? opt.hist_cap : 4096;
+  P.cost = p.cost;
+
+  // processing order
+  if (opt.order_mode == 1) {
+    greedy_colour_order(p, P.order);
+  } else if (opt.order_mode == 0) {
+    if (p.order.empty()) {
+      P.order.resize(size_t(n));
+      std::iota(P.order.begin(), P.order.end(), 0);
+    } else {
+      P.order = p.order;
+    }
+  } else {
+    return set_error(BDDMP_INVALID_ARG, "order_mode must be 0 or 1");
+  }
+  P.rank.assign(size_t(n), -1);
+  for (int32_t r = 0; r < n; ++r) P.rank[P.order[r]] = r;
+
+  // rows -> shapes (rows with the same coefficient sequence, sense and rhs share a shape)
+  std::unordered_map<std::string, int32_t> memo;
+  std::vector<int32_t> stamp(size_t(n), -1);
+  std::vector<std::pair<int32_t, int32_t>> items;  // (rank, nnz index)
+  std::vector<int64_t> coefs;
+  std::string key, err;
+  P.row_shape.assign(size_t(m), -1);
+  P.canon_off.assign(size_t(m) + 1, 0);
+  P.canon_node.assign(size_t(m) + 1, 0);
+  std::vector<int32_t> inc_row;
+  for (int32_t j = 0; j < m; ++j) {
+    const int64_t a0 = p.row_ptr[j], a1 = p.row_ptr[j + 1];
+    items.clear();
+    for (int64_t q = a0; q < a1; ++q) {
+      const int32_t v = p.col[q];
+      if (stamp[v] == j) return set_error(BDDMP_INVALID_ARG, "row " + std::to_string(j) + ": repeated column " + std::to_string(v));
+      stamp[v] = j;
+      if (p.coef[q] != 0) items.emplace_back(P.rank[v], int32_t(q));
+    }
+    std::sort(items.begin(), items.end());
+    const int32_t k = int32_t(items.size());
+    coefs.resize(size_t(k));
+    for (int32_t t = 0; t < k; ++t) coefs[t] = p.coef[items[t].second];
+    key.assign(1 + 8 + 8 * size_t(k), '\0');
+    key[0] = char(p.sense[j]);
+    std::memcpy(&key[1], &p.rhs[j], 8);
+    if (k) std::memcpy(&key[9], coefs.data(), 8 * size_t(k));
+    auto it = memo.find(key);
+    int32_t sid;
+    if (it == memo.end()) {
+      Shape sh;
+      const int32_t rc = build_shape(coefs.data(), k, p.sense[j], p.rhs[j], opt.node_budget, sh, err);
+      if (rc != BDDMP_OK) return set_error(rc, "row " + std::to_string(j) + ": " + err);
+      sid = int32_t(P.shapes.size());
+      P.shapes.push_back(std::move(sh));
+      memo.emplace(key, sid);
+    } else {
+      sid = it->second;
+    }
+    const Shape &sh = P.shapes[sid];
+    P.row_shape[j] = k ? sid : -1;
+    P.canon_off[j + 1] = P.canon_off[j] + k;
+    P.canon_node[j + 1] = P.canon_node[j] + sh.first[k];
+    for (int32_t t = 0; t < k; ++t) {
+      P.inc_var.push_back(p.col[items[t].second]);
+      inc_row.push_back(j);
+    }
+    P.max_width = std::max(P.max_width, sh.max_width);
+  }
+  P.I = P.canon_off[m];
+  P.N = P.canon_node[m];
+  if (opt.node_budget > 0 && P.N > opt.node_budget)
+    return set_error(BDDMP_BDD_TOO_LARGE, "total nodes " + std::to_string(P.N) + " exceed the node budget");
+  if (P.N >= INT32_MAX || P.I >= INT32_MAX) return set_error(BDDMP_BDD_TOO_LARGE, "more than 2^31 nodes or incidences");
+  const int64_t I = P.I;
+  for (int32_t j = 0; j < m; ++j) {
+    if (P.row_shape[j] < 0) continue;
+    const Shape &sh = P.shapes[P.row_shape[j]];
+    for (size_t u = 0; u < sh.lo.size(); ++u) {
+      P.live += (sh.lo[u] != -1) + (sh.hi[u] != -1);
+      P.bot += (sh.lo[u] == -1) + (sh.hi[u] == -1);
+    }
+  }
+
+  // J_i in ascending row order
+  P.var_nj.assign(size_t(n), 0);
+  for (int64_t c = 0; c < I; ++c) P.var_nj[P.inc_var[c]]++;
+  std::vector<int64_t> iptr(size_t(n) + 1, 0);
+  for (int32_t i = 0; i < n; ++i) iptr[i + 1] = iptr[i] + P.var_nj[i];
+  std::vector<int32_t> ilist(static_cast<size_t>(I));
+  {
+    std::vector<int64_t> fill(iptr.begin(), iptr.end() - 1);
+    for (int64_t c = 0; c < I; ++c) ilist[fill[P.inc_var[c]]++] = int32_t(c);
+  }
+  for (int32_t i = 0; i < n; ++i) P.max_j = std::max(P.max_j, P.var_nj[i]);
+  if (P.max_j > kBigMax)
+    return set_error(BDDMP_INVALID_ARG, "a variable appears in more than " + std::to_string(kBigMax) + " rows");
+
+  // statically forced variables: a level with no live 1-arc forces 0, none with a live 0-arc forces 1
+  for (int32_t i = 0; i < n; ++i) {
+    bool f0 = false, f1 = false;
+    for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
+      const int64_t c = ilist[q];
+      const int32_t j = inc_row[c];
+      const Shape &sh = P.shapes[P.row_shape[j]];
+      const int32_t l = int32_t(c - P.canon_off[j]);
+      bool live0 = false, live1 = false;
+      for (int32_t u = sh.first[l]; u < sh.first[l + 1]; ++u) {
+        live0 |= sh.lo[u] != -1;
+        live1 |= sh.hi[u] != -1;
+      }
+      f0 |= !live1;
+      f1 |= !live0;
+    }
+    if (f0 && f1) return set_error(BDDMP_CONFLICT, "rows force variable " + std::to_string(i) + " to both 0 and 1");
+  }
+
+  // dependency waves
+  P.wave_f.assign(size_t(n), 0);
+  P.wave_b.assign(size_t(n), 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t i = P.order[r];
+    if (!P.var_nj[i]) continue;
+    int32_t t = 0;
+    for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
+      const int64_t c = ilist[q];
+      if (c > P.canon_off[inc_row[c]]) t = std::max(t, P.wave_f[P.inc_var[c - 1]]);
+    }
+    P.wave_f[i] = t + 1;
+    P.Df = std::max(P.Df, t + 1);
+  }
+  for (int32_t r = n - 1; r >= 0; --r) {
+    const int32_t i = P.order[r];
+    if (!P.var_nj[i]) continue;
+    int32_t t = 0;
+    for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
+      const int64_t c = ilist[q];
+      if (c + 1 < P.canon_off[inc_row[c] + 1]) t = std::max(t, P.wave_b[P.inc_var[c + 1]]);
+    }
+    P.wave_b[i] = t + 1;
+    P.Db = std::max(P.Db, t + 1);
+  }
+
+  // forward-wave-major storage order of the variables: (wave_f, rank)
+  std::vector<std::vector<int32_t>> fw(size_t(P.Df) + 1), bw(size_t(P.Db) + 1);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t i = P.order[r];
+    if (P.var_nj[i]) {
+      fw[P.wave_f[i]].push_back(i);
+      bw[P.wave_b[i]].push_back(i);
+    }
+  }
+  P.canon_of.assign(size_t(I), 0);
+  P.layer_of.assign(size_t(I), 0);
+  P.layer_var.assign(size_t(I), 0);
+  P.seg.assign(size_t(I), 0);
+  P.var_first.assign(size_t(n), -1);
+  int64_t L = 0;
+  for (int32_t t = 1; t <= P.Df; ++t)
+    for (int32_t i : fw[t]) {
+      P.var_first[i] = int32_t(L);
+      const int32_t cnt = P.var_nj[i];
+      for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q, ++L) {
+        const int32_t c = ilist[q];
+        P.canon_of[L] = c;
+        P.layer_of[c] = int32_t(L);
+        P.layer_var[L] = i;
+        P.seg[L] = uint32_t(q - iptr[i]) | (uint32_t(cnt) << 16);
+      }
+    }
+  // nodes in layer order
+  P.node_off.assign(size_t(I) + 1, 0);
+  P.arcs.resize(size_t(P.N));
+  int64_t acc = 0;
+  auto code = [](int32_t c) -> uint32_t { return c == -1 ? kBot : (c == -2 ? kTop : uint32_t(c)); };
+  for (int64_t Lq = 0; Lq < I; ++Lq) {
+    const int32_t c = P.canon_of[Lq];
+    const int32_t j = inc_row[c];
+    const Shape &sh = P.shapes[P.row_shape[j]];
+    const int32_t l = int32_t(c - P.canon_off[j]);
+    P.node_off[Lq] = int32_t(acc);
+    for (int32_t u = sh.first[l]; u < sh.first[l + 1]; ++u) P.arcs[acc++] = code(sh.lo[u]) | (code(sh.hi[u]) << 16);
+  }
+  P.node_off[I] = int32_t(acc);
+  P.child_off.assign(size_t(I), -1);
+  for (int64_t Lq = 0; Lq < I; ++Lq) {
+    const int32_t c = P.canon_of[Lq];
+    if (c + 1 < P.canon_off[inc_row[c] + 1]) P.child_off[Lq] = P.node_off[P.layer_of[c + 1]];
+  }
+  P.root_node.assign(size_t(m), -1);
+  P.bdd_canon_off.assign(size_t(m) + 1, 0);
+  for (int32_t j = 0; j < m; ++j) {
+    P.bdd_canon_off[j + 1] = int32_t(P.canon_off[j + 1]);
+    if (P.canon_off[j + 1] > P.canon_off[j]) P.root_node[j] = P.node_off[P.layer_of[P.canon_off[j]]];
+  }
+
+  // forward tiles: positions are storage layers
+  int64_t pos = 0;
+  P.fwd_waves.resize(size_t(P.Df));
+  for (int32_t t = 1; t <= P.Df; ++t) {
+    tile_pass(fw[t], P.var_nj, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
+    P.fwd_waves[t - 1].list = 0;
+    for (int32_t i : fw[t]) pos += P.var_nj[i];
+  }
+  // backward order (wave_b, rank); a wave whose variables sit back to back in storage uses
+  // storage positions directly, otherwise positions go through bwd_list
+  P.bwd_list.assign(size_t(I), 0);
+  P.bwd_waves.resize(size_t(P.Db));
+  pos = 0;
+  for (int32_t t = 1; t <= P.Db; ++t) {
+    const int64_t w0 = pos;
+    bool contig = true;
+    for (int32_t i : bw[t])
+      for (int32_t q = 0; q < P.var_nj[i]; ++q, ++pos) {
+        P.bwd_list[pos] = P.var_first[i] + q;
+        if (P.bwd_list[pos] != P.bwd_list[w0] + (pos - w0)) contig = false;
+      }
+    WaveRange &wr = P.bwd_waves[t - 1];
+    tile_pass(bw[t], P.var_nj, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big, wr);
+    wr.list = contig ? 0 : 1;
+    P.bwd_contiguous = P.bwd_contiguous && contig;
+  }
+  if (P.bwd_contiguous) P.bwd_list.clear();
+
+  P.lb_const = 0.0;
+  for (int32_t i = 0; i < n; ++i)
+    if (!P.var_nj[i] && p.cost[i] < 0) P.lb_const += p.cost[i];
+
+  // arena layout
+  ArenaLayout &A = P.lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t N = size_t(P.N), In = size_t(I), nn = size_t(n), mm = size_t(m);
+  A.arcs = take(4 * N);
+  A.mf = take(4 * N);
+  A.mb = take(4 * N);
+  A.node_off = take(4 * (In + 1));
+  A.child_off = take(4 * In);
+  A.lam = take(4 * In);
+  A.seg = take(4 * In);
+  A.canon_of = take(4 * In);
+  A.layer_of = take(4 * In);
+  A.layer_var = take(4 * In);
+  A.fwd_tiles = take(4 * P.fwd_tiles.size());
+  A.bwd_tiles = take(4 * P.bwd_tiles.size());
+  A.bwd_list = take(4 * P.bwd_list.size());
+  A.fwd_big = take(4 * P.fwd_big.size());
+  A.bwd_big = take(4 * P.bwd_big.size());
+  A.root_node = take(4 * mm);
+  A.bdd_canon_off = take(4 * (mm + 1));
+  A.cost = take(8 * nn);
+  A.var_first = take(4 * nn);
+  A.var_nj = take(4 * nn);
+  A.d_fresh = take(4 * In);
+  A.mbuf = take(4 * nn);
+  A.xbuf = take(nn);
+  A.part = take(8 * 2 * size_t(kLbBlocks));
+  A.ipart = take(8 * size_t(kLbBlocks));
+  A.lb_hist = take(8 * size_t(P.hist_cap));
+  A.scal = take(256);
+  A.total = off;
+  const std::string bad = validate_layout(P);
+  if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);
+  return BDDMP_OK;
+}
+
+}  // namespace bddmp

@@ -1,0 +1,26 @@
+// Solver entry points shared by the C-ABI layer and the HIP translation unit.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "bddmp.h"
+
+namespace bddmp {
+
+struct Plan;
+struct Solver;
+
+int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solver *&out);
+int32_t solver_reset(Solver &S);
+int32_t solver_iterate(Solver &S, int32_t n);
+int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_lambda_bound);
+int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out);
+int32_t solver_min_marginals(Solver &S, float *m0, float *m1);
+int32_t solver_get_lambda(Solver &S, float *lam);
+int32_t solver_set_lambda(Solver &S, const float *lam);
+int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj, int64_t *nviol);
+int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out);
+void solver_destroy(Solver *S);
+
+}  // namespace bddmp

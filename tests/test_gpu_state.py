@@ -1,0 +1,152 @@
+"""GPU behaviour beyond element parity: determinism, checkpoint/resume, edge cases, argument errors,
+the timing entry point, and the full-size MRF workload (sampled against the oracle)."""
+import numpy as np
+import pytest
+
+from parity import assert_incidence_close, assert_trace_close, incidence_scale, run_gpu, run_oracle
+from oracle import Oracle
+from paper_2009_00481_amd import binding as B
+from paper_2009_00481_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(ilp, **kw):
+    prob = B.Problem.from_ilp(ilp)
+    plan = B.Plan(prob, **kw)
+    return B.Solver(plan), plan
+
+
+def test_two_runs_are_bitwise_equal():
+    ilp = I.config("5sub")
+    a = run_gpu(ilp, 30)
+    b = run_gpu(ilp, 30)
+    assert np.array_equal(a["lam"], b["lam"])
+    assert np.array_equal(a["hist"], b["hist"])
+    assert np.array_equal(a["m0"], b["m0"]) and np.array_equal(a["m1"], b["m1"])
+
+
+def test_checkpoint_resume_is_bitwise():
+    import torch
+
+    ilp = I.config(1)
+    s1, p1 = _solver(ilp)
+    s1.iterate(10)
+    ck = s1.get_lambda().clone()
+    s1.iterate(10)
+    lam_a = s1.get_lambda().cpu()
+    lb_a = s1.lower_bound()[0]
+    s2, p2 = _solver(ilp)
+    s2.set_lambda(ck)
+    s2.iterate(10)
+    lam_b = s2.get_lambda().cpu()
+    lb_b = s2.lower_bound()[0]
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a, lam_b)
+    assert lb_a == lb_b
+
+
+def test_problem_without_rows():
+    cost = np.array([1.0, -2.0, 0.5, -0.25])
+    ilp = I.from_rows(4, cost, [])
+    g = run_gpu(ilp, 3)
+    assert g["lb"] == pytest.approx(-2.25)
+    assert g["x"].tolist() == [0, 1, 0, 1]
+    assert g["obj"] == pytest.approx(-2.25)
+    assert g["nviol"] == 0
+
+
+def test_empty_rows_unconstrained_and_single_levels():
+    rows = [([], [], 1, 0), ([0, 1], [1, 1], 1, 1), ([2], [1], 1, 0), ([3], [2], 2, 1), ([1, 3], [1, -1], 1, 0)]
+    cost = np.array([-1.0, -0.5, 0.75, 0.25, -3.0])  # variable 4 is in no row
+    ilp = I.from_rows(5, cost, rows)
+    g = run_gpu(ilp, 6)
+    r = run_oracle(ilp, 6, "f32")
+    np.testing.assert_allclose(g["hist"], r["hist"], rtol=1e-12)
+    assert np.array_equal(g["lam"], r["lam"])
+    assert np.array_equal(g["x"], r["x"])
+    assert g["x"][4] == 1
+
+
+def test_backward_list_path_is_exercised():
+    ilp = I.random_ilp(40, 30, kmin=1, kmax=10, cmax=3, seed=0)
+    prob = B.Problem.from_ilp(ilp)
+    plan = B.Plan(prob)
+    assert plan.stats.bwd_contiguous == 0
+
+
+def test_bind_argument_errors():
+    import torch
+
+    ilp = I.config(1)
+    prob = B.Problem.from_ilp(ilp)
+    plan = B.Plan(prob)
+    nb = int(plan.stats.device_bytes)
+    small = torch.empty(nb - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_bind(plan.h, small, nb - 256, torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == -1
+    big = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_bind(plan.h, big[4:], nb, torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == -1
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_iterate(None, 1)
+    assert e.value.code == -7
+
+
+def test_time_kernels_counts_launches():
+    ilp = I.config(1)
+    s, plan = _solver(ilp)
+    t = s.time_kernels(3)
+    st = plan.stats
+    assert t["fwd_launches"] == 3 * st.waves_fwd and t["bwd_launches"] == 3 * st.waves_bwd
+    assert t["fwd_ms"] > 0 and t["bwd_ms"] > 0 and t["iter_ms"] > 0
+    assert t["fwd_bytes"] == pytest.approx(3 * (20 * st.n_nodes + 8 * st.n_incidences))
+    # the solver advanced 6 iterations and stays consistent with the oracle
+    r = Oracle(ilp)
+    r.init()
+    tr = r.iterate(6)
+    assert s.lower_bound()[0] == pytest.approx(tr[-1], rel=1e-4)
+
+
+def test_full_size_mrf_workload():
+    """Potts 256x256, 8 labels (the benchmark workload) at the benchmark's launch configuration:
+    the first bounds and sampled multipliers against the oracle, then the whole 500-iteration run
+    checked by properties (monotone bound within float rounding, dual feasibility, finiteness)."""
+    import torch
+
+    ilp = I.config(2)
+    print("[cfg2] plan", flush=True)
+    s, plan = _solver(ilp, hist_cap=1024)
+    s.iterate(2)
+    lam2 = s.get_lambda().cpu().numpy().astype(np.float64)
+    m0, m1 = s.min_marginals()
+    m0 = m0.cpu().numpy().astype(np.float64)
+    m1 = m1.cpu().numpy().astype(np.float64)
+    hist2 = s.lb_history(3)
+    print("[cfg2] oracle", flush=True)
+    o = Oracle(ilp)
+    lb0 = o.init()
+    tr = o.iterate(2)
+    lam_ref = o.lam()
+    assert_trace_close(hist2, np.concatenate([[lb0], tr]))
+    rng = np.random.default_rng(0)
+    idx = rng.choice(lam_ref.shape[0], size=200_000, replace=False)
+    scale = incidence_scale(ilp, lam_ref)
+    assert_incidence_close(lam2[idx], lam_ref[idx], scale[idx], what="lambda (sampled)")
+    r0, r1 = o.min_marginals()
+    assert_incidence_close(m0[idx], r0[idx], scale[idx], what="m0 (sampled)")
+    assert_incidence_close(m1[idx], r1[idx], scale[idx], what="m1 (sampled)")
+    del o
+    print("[cfg2] 498 more iterations", flush=True)
+    s.iterate(498)
+    lb, resid, any_lb = s.lower_bound()
+    hist = s.lb_history(1024)
+    torch.cuda.synchronize()
+    assert hist.shape[0] == 501 and np.all(np.isfinite(hist))
+    drop = np.diff(hist)
+    assert np.all(drop >= -1e-6 * np.abs(hist[1:])), drop.min()
+    assert hist[-1] > hist[0]
+    assert resid <= 1e-4 * float(np.abs(ilp.cost).max())
+    assert any_lb <= lb + 1e-9

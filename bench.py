@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -61,6 +63,15 @@ def main():
 
     from paper_2009_00481_amd import binding as B
     from paper_2009_00481_amd import instances as I
+
+    if args.copy_probe_mib:
+        # a plain copy kernel of known size: reads and writes copy_probe_mib MiB once each
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg, T = WORKLOADS[args.workload]
     if args.iters:

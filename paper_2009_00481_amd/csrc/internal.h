@@ -9,7 +9,7 @@
 
 namespace bddmp {
 
-// Child codes of the 16-bit packed arcs: an in-level index of the next level, or a terminal.
+// 16-bit child codes of the general arc array: an in-level index of the next level, or a terminal.
 constexpr uint32_t kBot = 0xFFFFu;
 constexpr uint32_t kTop = 0xFFFEu;
 constexpr int32_t kMaxWidth = 0x7FFF;   // widest level the 16-bit child codes can address
@@ -17,12 +17,19 @@ constexpr int kTile = 256;              // layers per workgroup of the wave kern
 constexpr int kBigMax = 4096;           // max rows of one variable (J_i) a wave kernel handles
 constexpr int kLbBlocks = 1024;         // fixed partial count of the deterministic fp64 reductions
 
-struct Error {
-  int32_t code;
-  std::string msg;
-};
+// 2-bit child codes of a narrow layer (both its level and the next have at most 2 nodes)
+constexpr uint32_t kC2Bot = 2u, kC2Top = 3u;
 
-// Records the message for bddmp_last_error and returns code.
+// Layer record meta word: bits 0-7 arcs of a narrow layer (node u: lo at 4u, hi at 4u+2),
+// bits 8-9 own width of a narrow layer (0 marks a general layer), bit 10 root level,
+// bits 11-20 position in the variable's segment, bits 21-30 segment length (<= 1023 in tiles).
+constexpr uint32_t kMetaWidthShift = 8, kMetaRootBit = 1u << 10, kMetaPosShift = 11, kMetaLenShift = 21;
+constexpr uint32_t kMetaField = 0x3FFu;
+
+// Bit 31 of a backward tile's end position: the tile holds a root level (contributes to the bound).
+constexpr uint32_t kTileRootBit = 0x80000000u;
+
+// Records bddmp_last_error's message and returns code.
 int32_t set_error(int32_t code, const std::string &msg);
 
 // One canonical diagram shape: levels, per-level widths, level-relative children (-1 BOT, -2 TOP).
@@ -51,10 +58,10 @@ struct Problem {
 
 // Byte offsets of the solver's arrays inside the device arena.
 struct ArenaLayout {
-  size_t arcs, mf, mb, node_off, child_off, lam, seg, canon_of, layer_of, layer_var;
+  size_t meta, child, parent, lam, mf, mbc, garcs, grec, canon_of, layer_of, layer_var, root_slot;
   size_t fwd_tiles, bwd_tiles, bwd_list, fwd_big, bwd_big;
-  size_t root_node, bdd_canon_off, cost, var_first, var_nj;
-  size_t d_fresh, mbuf, xbuf, part, ipart, lb_hist, scal;
+  size_t bdd_canon_off, cost, var_first, var_nj;
+  size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
   size_t total;
 };
 
@@ -62,11 +69,15 @@ struct WaveRange {
   int32_t tile_begin, tile_end;  // normal tiles [begin, end) in the pass's tile list
   int32_t big_begin, big_end;    // big tiles (one variable with more than kTile rows)
   int32_t list;                  // backward pass: 1 if positions go through bwd_list
+  int64_t nodes, layers;         // work of the wave (for the byte model)
 };
 
 struct Plan {
   int32_t n = 0, m = 0;
   int64_t N = 0, I = 0, live = 0, bot = 0;
+  int64_t S = 0;                      // own-level slots: 2 per layer, then the nodes of wider levels
+  int64_t Sc = 0;                     // child-level slots, the same way for the next level
+  int64_t n_general = 0;              // layers outside the narrow class
   int32_t max_width = 0, max_j = 0;
   std::vector<Shape> shapes;
   std::vector<int32_t> row_shape;     // [m], -1 for a row without variables
@@ -78,24 +89,27 @@ struct Plan {
   int32_t Df = 0, Db = 0;
   double lb_const = 0.0;              // sum of min(0, c_i) over variables in no row
   std::vector<double> cost;
-  // host images of the device arrays (storage = forward-wave-major layer order)
-  std::vector<uint32_t> arcs;         // [N] lo | hi << 16
-  std::vector<int32_t> node_off;      // [I+1]
-  std::vector<int32_t> child_off;     // [I], -1 on a last level
-  std::vector<uint32_t> seg;          // [I] position in the variable's segment | length << 16
+  // host images of the device arrays (layers in forward-wave-major order)
+  std::vector<uint32_t> meta;         // [I] meta word of each layer
+  std::vector<int32_t> child, parent; // [I] next / previous level of the same row, -1 at the ends
+  std::vector<uint32_t> garcs;        // [S] lo | hi << 16 (16-bit codes) at every node slot
+  std::vector<int32_t> grec;          // [4I] or empty: own slot, own width, child slot, child width
   std::vector<int32_t> canon_of;      // [I] storage layer -> canonical incidence
   std::vector<int32_t> layer_of;      // [I] canonical incidence -> storage layer
   std::vector<int32_t> layer_var;     // [I] variable of a storage layer
-  std::vector<int32_t> fwd_tiles, bwd_tiles;  // tile start positions (+ end sentinel)
-  std::vector<int32_t> fwd_big, bwd_big;      // big tiles as (start, end) position pairs
+  std::vector<int32_t> root_slot;     // [m] slot of the root node, -1 for rows without variables
+  std::vector<int32_t> fwd_tiles, bwd_tiles;  // tiles as (start, end) position pairs
+  std::vector<int32_t> fwd_big, bwd_big;      // big tiles (one variable each) as (start, end) pairs
   std::vector<int32_t> bwd_list;      // [I] backward position -> storage layer (used if not contiguous)
   std::vector<WaveRange> fwd_waves, bwd_waves;
   bool bwd_contiguous = true;
-  std::vector<int32_t> root_node;     // [m] node of the root, -1 for rows without variables
   std::vector<int32_t> bdd_canon_off; // [m+1] as int32 for the device
   std::vector<int32_t> var_first;     // [n] first storage layer of the variable, -1 if none
   std::vector<int32_t> var_nj;        // [n] |J_i|
+  // own slot of a layer (device code derives it the same way)
+  std::vector<int64_t> own_slot, cslot; // [I] own-level slot and child-level slot
   int32_t hist_cap = 4096;
+  int64_t n_lbpart = 0;               // backward tiles (normal + big) = bound partials per sweep
   ArenaLayout lay{};
 };
 

@@ -97,78 +97,97 @@ void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj,
 }
 
 // Checks every index the wave, bound and output kernels read or write against the array it
-// addresses, and that tiles hold whole variable segments. Returns an empty string when sound.
-std::string validate_layout(const Plan &P) {
-  const int64_t I = P.I, N = P.N;
-  if (int64_t(P.node_off.size()) != I + 1 || P.node_off[0] != 0 || P.node_off[I] != N) return "node_off";
+// addresses, that narrow records decode to the same arcs as the general array, and that tiles hold
+// whole variable segments and cover every layer once per pass. Returns an empty string when sound.
+std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, const std::vector<int32_t> &childw,
+                            const std::vector<int32_t> &level) {
+  const int64_t I = P.I, S = P.S;
+  if (int64_t(P.meta.size()) != I || int64_t(P.child.size()) != I || int64_t(P.parent.size()) != I ||
+      int64_t(P.garcs.size()) != S)
+    return "array sizes";
   for (int64_t L = 0; L < I; ++L) {
-    const int32_t no = P.node_off[L], w = P.node_off[L + 1] - no;
-    if (w <= 0 || w > kMaxWidth) return "layer width";
-    const int32_t co = P.child_off[L];
-    int32_t wc = 0;
-    if (co >= 0) {
-      const int32_t c = P.canon_of[L];
-      const int32_t Lc = P.layer_of[c + 1];
-      if (co != P.node_off[Lc]) return "child_off";
-      wc = P.node_off[Lc + 1] - co;
-    }
+    const int64_t os = P.own_slot[L];
+    const int32_t w = ownw[L], wc = childw[L];
+    if (w <= 0 || w > kMaxWidth || os < 0 || os + w > S) return "own slots";
+    if (w <= 2 && os != 2 * L) return "narrow slot";
+    const int64_t cs = P.cslot[L];
+    if (cs < 0 || cs + wc > P.Sc || (wc <= 2 && cs != 2 * L)) return "child slots";
+    const int32_t cl = P.child[L];
+    const uint32_t meta = P.meta[L];
+    if ((cl < 0) != (wc == 0)) return "child layer";
+    if (cl >= 0 && (cl >= I || P.canon_of[cl] != P.canon_of[L] + 1 || ownw[cl] != wc || P.parent[cl] != L))
+      return "child layer";
+    const int32_t pl = P.parent[L];
+    if ((pl < 0) != (level[L] == 0)) return "parent layer";
+    if (pl >= 0 && (pl >= I || P.child[pl] != L || childw[pl] != w)) return "parent layer";
     for (int32_t u = 0; u < w; ++u) {
-      const uint32_t a = P.arcs[no + u];
+      const uint32_t a = P.garcs[size_t(os + u)];
       for (uint32_t ch : {a & 0xFFFFu, a >> 16}) {
         if (ch == kBot) continue;
         if (ch == kTop) {
-          if (co >= 0) return "TOP before the last level";
+          if (cl >= 0) return "TOP before the last level";
           continue;
         }
-        if (co < 0 || int32_t(ch) >= wc) return "child index outside the next level";
+        if (cl < 0 || int32_t(ch) >= wc) return "child index outside the next level";
       }
     }
-    const uint32_t pos = P.seg[L] & 0xFFFFu, len = P.seg[L] >> 16;
-    if (len == 0 || pos >= len || int32_t(len) != P.var_nj[P.layer_var[L]]) return "segment";
+    const uint32_t w2 = (meta >> kMetaWidthShift) & 3u;
+    const bool narrow = w <= 2 && wc <= 2;
+    if (narrow != (w2 != 0) || (narrow && int32_t(w2) != w)) return "narrow flag";
+    if (narrow) {
+      for (int32_t u = 0; u < 2; ++u) {
+        const uint32_t a = u < w ? P.garcs[size_t(os + u)] : (kBot | (kBot << 16));
+        for (int beta = 0; beta < 2; ++beta) {
+          const uint32_t c16 = beta ? a >> 16 : a & 0xFFFFu;
+          const uint32_t c2 = (meta >> (4 * u + 2 * beta)) & 3u;
+          const uint32_t want = c16 == kBot ? kC2Bot : (c16 == kTop ? kC2Top : c16);
+          if (c2 != want) return "narrow arcs";
+        }
+      }
+    } else {
+      if (P.grec.empty()) return "general record missing";
+      const int32_t *g = &P.grec[4 * size_t(L)];
+      if (g[0] != os || g[1] != w || g[2] != cs || g[3] != wc) return "general record";
+    }
+    if (((meta & kMetaRootBit) != 0) != (level[L] == 0)) return "root flag";
+    const uint32_t pos = (meta >> kMetaPosShift) & kMetaField, len = (meta >> kMetaLenShift) & kMetaField;
+    const int32_t nj = P.var_nj[P.layer_var[L]];
+    if (len == 0 || pos >= len || int32_t(len) != std::min<int32_t>(nj, int32_t(kMetaField))) return "segment";
     if (P.layer_of[P.canon_of[L]] != L) return "canon_of / layer_of";
   }
-  auto check_tiles = [&](const std::vector<int32_t> &tiles, const std::vector<WaveRange> &waves, bool fwd,
-                         bool big) -> std::string {
-    for (const WaveRange &wr : waves) {
-      const int32_t b0 = big ? wr.big_begin : wr.tile_begin, b1 = big ? wr.big_end : wr.tile_end;
-      for (int32_t t = b0; t < b1; ++t) {
-        const int64_t p0 = tiles[2 * size_t(t)], p1 = tiles[2 * size_t(t) + 1];
-        const int64_t cap = big ? kBigMax : kTile;
-        if (p1 <= p0 || p1 - p0 > cap || p0 < 0 || p1 > I) return "tile bounds";
-        auto layer = [&](int64_t p) -> int64_t { return (!fwd && wr.list) ? P.bwd_list[size_t(p)] : p; };
-        const int64_t Lf = layer(p0), Ll = layer(p1 - 1);
-        if (Lf < 0 || Lf >= I || Ll < 0 || Ll >= I) return "tile layer";
-        if ((P.seg[Lf] & 0xFFFFu) != 0) return "tile starts inside a segment";
-        if ((P.seg[Ll] & 0xFFFFu) != (P.seg[Ll] >> 16) - 1) return "tile ends inside a segment";
-        if (big && (P.seg[Lf] >> 16) != uint32_t(p1 - p0)) return "big tile is not one variable";
-      }
-    }
-    return "";
-  };
-  for (auto r : {check_tiles(P.fwd_tiles, P.fwd_waves, true, false), check_tiles(P.fwd_big, P.fwd_waves, true, true),
-                 check_tiles(P.bwd_tiles, P.bwd_waves, false, false), check_tiles(P.bwd_big, P.bwd_waves, false, true)})
-    if (!r.empty()) return r;
-  // every layer is visited exactly once per pass, in a position whose segment slot matches
+  // every layer is visited exactly once per pass; a normal tile holds whole segments of variables
+  // with at most kTile rows, a big tile exactly one variable
   for (int pass = 0; pass < 2; ++pass) {
     std::vector<uint8_t> seen(size_t(I), 0);
     const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
     for (const WaveRange &wr : waves)
       for (int big = 0; big < 2; ++big) {
         const auto &tiles = pass ? (big ? P.bwd_big : P.bwd_tiles) : (big ? P.fwd_big : P.fwd_tiles);
-        for (int32_t t = big ? wr.big_begin : wr.tile_begin; t < (big ? wr.big_end : wr.tile_end); ++t)
-          for (int64_t p = tiles[2 * size_t(t)]; p < tiles[2 * size_t(t) + 1]; ++p) {
+        for (int32_t t = big ? wr.big_begin : wr.tile_begin; t < (big ? wr.big_end : wr.tile_end); ++t) {
+          const int64_t p0 = tiles[2 * size_t(t)], p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          const int64_t cap = big ? kBigMax : kTile;
+          if (p1 <= p0 || p1 - p0 > cap || p0 < 0 || p1 > I) return "tile bounds";
+          for (int64_t p = p0; p < p1; ++p) {
             const int64_t L = (pass && wr.list) ? P.bwd_list[size_t(p)] : p;
+            if (L < 0 || L >= I) return "tile layer";
             if (seen[L]++) return "layer visited twice in a pass";
-            const int64_t head = p - int64_t(P.seg[L] & 0xFFFFu);
-            if (head < tiles[2 * size_t(t)] || head + int64_t(P.seg[L] >> 16) > tiles[2 * size_t(t) + 1])
-              return "segment leaves its tile";
+            const int32_t nj = P.var_nj[P.layer_var[L]];
+            if (big) {
+              if (nj != p1 - p0 || P.layer_var[L] != P.layer_var[(pass && wr.list) ? P.bwd_list[size_t(p0)] : p0])
+                return "big tile is not one variable";
+              continue;
+            }
+            const uint32_t meta = P.meta[L];
+            const int64_t head = p - int64_t((meta >> kMetaPosShift) & kMetaField);
+            if (nj > kTile || head < p0 || head + nj > p1) return "segment leaves its tile";
           }
+        }
       }
     for (int64_t L = 0; L < I; ++L)
       if (!seen[L]) return "layer missing from a pass";
   }
   for (int32_t j = 0; j < P.m; ++j)
-    if (P.root_node[j] >= N || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
+    if (P.root_slot[j] >= S || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
   for (int32_t i = 0; i < P.n; ++i)
     if (P.var_nj[i] && (P.var_first[i] < 0 || P.var_first[i] + P.var_nj[i] > I)) return "var_first";
   return "";
@@ -326,7 +345,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.Db = std::max(P.Db, t + 1);
   }
 
-  // forward-wave-major storage order of the variables: (wave_f, rank)
+  // Storage order. Wave 1 takes its variables in processing order; every later wave sorts its
+  // variables by the storage position of their earliest parent layer (the previous level of one of
+  // their rows), ties and parentless variables by processing order. A workgroup's layers then
+  // push to and read from next-level slots that sit together, instead of cache lines shared with
+  // other workgroups (and other XCDs).
   std::vector<std::vector<int32_t>> fw(size_t(P.Df) + 1), bw(size_t(P.Db) + 1);
   for (int32_t r = 0; r < n; ++r) {
     const int32_t i = P.order[r];
@@ -336,55 +359,148 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     }
   }
   P.canon_of.assign(size_t(I), 0);
-  P.layer_of.assign(size_t(I), 0);
+  P.layer_of.assign(size_t(I), -1);
   P.layer_var.assign(size_t(I), 0);
-  P.seg.assign(size_t(I), 0);
   P.var_first.assign(size_t(n), -1);
+  std::vector<uint32_t> segpos(size_t(I), 0);
   int64_t L = 0;
-  for (int32_t t = 1; t <= P.Df; ++t)
+  std::vector<std::pair<int64_t, int32_t>> keyed;
+  for (int32_t t = 1; t <= P.Df; ++t) {
+    keyed.clear();
+    for (int32_t i : fw[t]) {
+      int64_t key = INT64_MAX;
+      for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
+        const int32_t c = ilist[q];
+        if (c > P.canon_off[inc_row[c]]) key = std::min<int64_t>(key, P.layer_of[c - 1]);
+      }
+      keyed.emplace_back(key, P.rank[i]);
+    }
+    std::sort(keyed.begin(), keyed.end());
+    for (size_t q0 = 0; q0 < keyed.size(); ++q0) fw[t][q0] = P.order[keyed[q0].second];
     for (int32_t i : fw[t]) {
       P.var_first[i] = int32_t(L);
-      const int32_t cnt = P.var_nj[i];
       for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q, ++L) {
         const int32_t c = ilist[q];
         P.canon_of[L] = c;
         P.layer_of[c] = int32_t(L);
         P.layer_var[L] = i;
-        P.seg[L] = uint32_t(q - iptr[i]) | (uint32_t(cnt) << 16);
+        segpos[L] = uint32_t(q - iptr[i]);
       }
     }
-  // nodes in layer order
-  P.node_off.assign(size_t(I) + 1, 0);
-  P.arcs.resize(size_t(P.N));
-  int64_t acc = 0;
-  auto code = [](int32_t c) -> uint32_t { return c == -1 ? kBot : (c == -2 ? kTop : uint32_t(c)); };
+  }
+  // a backward wave lists its variables in storage order, so that a backward wave holding the
+  // same variables as a forward wave is one contiguous layer range
+  for (int32_t t = 1; t <= P.Db; ++t)
+    std::sort(bw[t].begin(), bw[t].end(), [&](int32_t x, int32_t y) { return P.var_first[x] < P.var_first[y]; });
+
+  // node slots: a level of at most 2 nodes sits at slots 2L, 2L+1 (the second one padding when it
+  // has one node); wider levels follow after 2I, in layer order
+  const size_t In0 = static_cast<size_t>(I);
+  std::vector<int32_t> ownw(In0), childw(In0, 0), child_layer(In0, -1), level(In0);
   for (int64_t Lq = 0; Lq < I; ++Lq) {
     const int32_t c = P.canon_of[Lq];
     const int32_t j = inc_row[c];
     const Shape &sh = P.shapes[P.row_shape[j]];
     const int32_t l = int32_t(c - P.canon_off[j]);
-    P.node_off[Lq] = int32_t(acc);
-    for (int32_t u = sh.first[l]; u < sh.first[l + 1]; ++u) P.arcs[acc++] = code(sh.lo[u]) | (code(sh.hi[u]) << 16);
+    level[Lq] = l;
+    ownw[Lq] = sh.first[l + 1] - sh.first[l];
+    if (l + 1 < sh.k) {
+      childw[Lq] = sh.first[l + 2] - sh.first[l + 1];
+      child_layer[Lq] = P.layer_of[c + 1];
+    }
   }
-  P.node_off[I] = int32_t(acc);
-  P.child_off.assign(size_t(I), -1);
+  // Forward messages of a layer's own level sit at its own slots; the backward messages of its
+  // child level are kept in a second slot space at its child slots, written there by the child
+  // layer's backward step. Both spaces put levels of at most 2 nodes at 2L, 2L+1.
+  P.own_slot.assign(size_t(I), 0);
+  P.cslot.assign(size_t(I), 0);
+  int64_t wide = 0, cwide = 0;
+  for (int64_t Lq = 0; Lq < I; ++Lq) {
+    if (ownw[Lq] <= 2) {
+      P.own_slot[Lq] = 2 * Lq;
+    } else {
+      P.own_slot[Lq] = 2 * I + wide;
+      wide += ownw[Lq];
+    }
+    if (childw[Lq] <= 2) {
+      P.cslot[Lq] = 2 * Lq;
+    } else {
+      P.cslot[Lq] = 2 * I + cwide;
+      cwide += childw[Lq];
+    }
+  }
+  P.S = 2 * I + wide;
+  P.Sc = 2 * I + cwide;
+  if (P.S >= INT32_MAX || P.Sc >= INT32_MAX) return set_error(BDDMP_BDD_TOO_LARGE, "more than 2^31 node slots");
+  auto code16 = [](int32_t c) -> uint32_t { return c == -1 ? kBot : (c == -2 ? kTop : uint32_t(c)); };
+  auto code2 = [](int32_t c) -> uint32_t { return c == -1 ? kC2Bot : (c == -2 ? kC2Top : uint32_t(c)); };
+  P.garcs.assign(size_t(P.S), kBot | (kBot << 16));
+  P.meta.assign(size_t(I), 0);
+  P.child.assign(size_t(I), -1);
+  P.parent.assign(size_t(I), -1);
+  for (int64_t Lq = 0; Lq < I; ++Lq) {
+    P.child[Lq] = child_layer[Lq];
+    if (child_layer[Lq] >= 0) P.parent[child_layer[Lq]] = int32_t(Lq);
+  }
+  P.n_general = 0;
   for (int64_t Lq = 0; Lq < I; ++Lq) {
     const int32_t c = P.canon_of[Lq];
-    if (c + 1 < P.canon_off[inc_row[c] + 1]) P.child_off[Lq] = P.node_off[P.layer_of[c + 1]];
+    const int32_t j = inc_row[c];
+    const Shape &sh = P.shapes[P.row_shape[j]];
+    const int32_t l = level[Lq];
+    const bool narrow = ownw[Lq] <= 2 && childw[Lq] <= 2;
+    uint32_t meta = 0;
+    for (int32_t u = 0; u < ownw[Lq]; ++u) {
+      const int32_t lo = sh.lo[sh.first[l] + u], hi = sh.hi[sh.first[l] + u];
+      P.garcs[size_t(P.own_slot[Lq] + u)] = code16(lo) | (code16(hi) << 16);
+    }
+    if (narrow) {
+      for (int32_t u = 0; u < 2; ++u) {
+        const uint32_t lo = u < ownw[Lq] ? code2(sh.lo[sh.first[l] + u]) : kC2Bot;
+        const uint32_t hi = u < ownw[Lq] ? code2(sh.hi[sh.first[l] + u]) : kC2Bot;
+        meta |= (lo | (hi << 2)) << (4 * u);
+      }
+      meta |= uint32_t(ownw[Lq]) << kMetaWidthShift;
+    } else {
+      ++P.n_general;
+    }
+    if (l == 0) meta |= kMetaRootBit;
+    const uint32_t len = uint32_t(std::min<int32_t>(P.var_nj[P.layer_var[Lq]], int32_t(kMetaField)));
+    meta |= (std::min<uint32_t>(segpos[Lq], kMetaField) << kMetaPosShift) | (len << kMetaLenShift);
+    P.meta[Lq] = meta;
   }
-  P.root_node.assign(size_t(m), -1);
+  if (P.n_general) {
+    P.grec.assign(4 * size_t(I), 0);
+    for (int64_t Lq = 0; Lq < I; ++Lq) {
+      P.grec[4 * size_t(Lq) + 0] = int32_t(P.own_slot[Lq]);
+      P.grec[4 * size_t(Lq) + 1] = ownw[Lq];
+      P.grec[4 * size_t(Lq) + 2] = int32_t(P.cslot[Lq]);
+      P.grec[4 * size_t(Lq) + 3] = childw[Lq];
+    }
+  }
+  P.root_slot.assign(size_t(m), -1);
   P.bdd_canon_off.assign(size_t(m) + 1, 0);
   for (int32_t j = 0; j < m; ++j) {
     P.bdd_canon_off[j + 1] = int32_t(P.canon_off[j + 1]);
-    if (P.canon_off[j + 1] > P.canon_off[j]) P.root_node[j] = P.node_off[P.layer_of[P.canon_off[j]]];
+    if (P.canon_off[j + 1] > P.canon_off[j]) P.root_slot[j] = int32_t(P.own_slot[P.layer_of[P.canon_off[j]]]);
   }
 
   // forward tiles: positions are storage layers
   int64_t pos = 0;
   P.fwd_waves.resize(size_t(P.Df));
+  auto wave_work = [&](const std::vector<int32_t> &vars, WaveRange &wr) {
+    wr.nodes = 0;
+    wr.layers = 0;
+    for (int32_t i : vars)
+      for (int32_t q = 0; q < P.var_nj[i]; ++q) {
+        wr.nodes += ownw[P.var_first[i] + q];
+        wr.layers += 1;
+      }
+  };
   for (int32_t t = 1; t <= P.Df; ++t) {
     tile_pass(fw[t], P.var_nj, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
     P.fwd_waves[t - 1].list = 0;
+    wave_work(fw[t], P.fwd_waves[t - 1]);
     for (int32_t i : fw[t]) pos += P.var_nj[i];
   }
   // backward order (wave_b, rank); a wave whose variables sit back to back in storage uses
@@ -403,9 +519,22 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     WaveRange &wr = P.bwd_waves[t - 1];
     tile_pass(bw[t], P.var_nj, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big, wr);
     wr.list = contig ? 0 : 1;
+    wave_work(bw[t], wr);
     P.bwd_contiguous = P.bwd_contiguous && contig;
   }
   if (P.bwd_contiguous) P.bwd_list.clear();
+  // flag backward tiles holding a root level; bound partials: one per wavefront of a normal tile,
+  // one per big tile
+  for (const WaveRange &wr : P.bwd_waves)
+    for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+      bool roots = false;
+      for (int64_t q = P.bwd_tiles[2 * size_t(t)]; q < P.bwd_tiles[2 * size_t(t) + 1]; ++q) {
+        const int64_t Lq = wr.list ? P.bwd_list[size_t(q)] : q;
+        roots = roots || level[Lq] == 0;
+      }
+      if (roots) P.bwd_tiles[2 * size_t(t) + 1] = int32_t(uint32_t(P.bwd_tiles[2 * size_t(t) + 1]) | kTileRootBit);
+    }
+  P.n_lbpart = int64_t(kTile / 64) * int64_t(P.bwd_tiles.size() / 2) + int64_t(P.bwd_big.size() / 2);
 
   P.lb_const = 0.0;
   for (int32_t i = 0; i < n; ++i)
@@ -419,23 +548,24 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     off = align256(off + bytes);
     return o;
   };
-  const size_t N = size_t(P.N), In = size_t(I), nn = size_t(n), mm = size_t(m);
-  A.arcs = take(4 * N);
-  A.mf = take(4 * N);
-  A.mb = take(4 * N);
-  A.node_off = take(4 * (In + 1));
-  A.child_off = take(4 * In);
+  const size_t In = size_t(I), nn = size_t(n), mm = size_t(m), S = size_t(P.S);
+  A.meta = take(4 * In);
+  A.child = take(4 * In);
+  A.parent = take(4 * In);
   A.lam = take(4 * In);
-  A.seg = take(4 * In);
+  A.mf = take(4 * S + 16);
+  A.mbc = take(4 * size_t(P.Sc) + 16);
+  A.garcs = take(4 * S);
+  A.grec = take(4 * P.grec.size());
   A.canon_of = take(4 * In);
   A.layer_of = take(4 * In);
   A.layer_var = take(4 * In);
+  A.root_slot = take(4 * mm);
   A.fwd_tiles = take(4 * P.fwd_tiles.size());
   A.bwd_tiles = take(4 * P.bwd_tiles.size());
   A.bwd_list = take(4 * P.bwd_list.size());
   A.fwd_big = take(4 * P.fwd_big.size());
   A.bwd_big = take(4 * P.bwd_big.size());
-  A.root_node = take(4 * mm);
   A.bdd_canon_off = take(4 * (mm + 1));
   A.cost = take(8 * nn);
   A.var_first = take(4 * nn);
@@ -444,11 +574,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.mbuf = take(4 * nn);
   A.xbuf = take(nn);
   A.part = take(8 * 2 * size_t(kLbBlocks));
-  A.ipart = take(8 * size_t(kLbBlocks));
+  A.lbpart = take(8 * size_t(P.n_lbpart + 1));
   A.lb_hist = take(8 * size_t(P.hist_cap));
   A.scal = take(256);
   A.total = off;
-  const std::string bad = validate_layout(P);
+  const std::string bad = validate_layout(P, ownw, childw, level);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);
   return BDDMP_OK;
 }

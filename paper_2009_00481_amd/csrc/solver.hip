@@ -4,9 +4,14 @@
 // One wave kernel launch runs every layer (one BDD level of one row) whose variable belongs to the
 // wave. A workgroup takes a tile of up to 256 consecutive layers; a variable's layers (its rows
 // J_i, ascending) never straddle tiles, so the J_i sum is a workgroup-local LDS reduction. One
-// lane handles one layer: narrow levels (<= 4 nodes, the MRF / matching / tracking shapes) keep
-// their nodes in registers; wider ones loop over nodes. Loads are coalesced because consecutive
-// lanes own consecutive layers, whose nodes are consecutive in the forward-wave-major layout.
+// lane handles one layer.
+//
+// Narrow layers (the level and the next one have at most 2 nodes: every MRF, matching and
+// tracking row) need a meta word (arcs as 2-bit codes, width, root flag, segment), the child or
+// parent layer index, the multiplier, and two float2 message pairs at slot 2L: the own level's
+// forward messages and the child level's backward messages. All loads are at the layer's own
+// index and issue together; only the two float2 stores scatter. Wider layers read a general
+// record and loop over their nodes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,65 +32,34 @@ constexpr int kNoUpdate = 1; // step only (initial backward sweep)
 constexpr int kExtract = 2;  // min-marginals to the outputs, then step with unchanged multipliers
 
 struct Dev {
-  const uint32_t *arcs;
-  float *mf, *mb;
-  const int32_t *node_off, *child_off;
+  const uint32_t *meta;
+  const int32_t *child, *parent;
   float *lam;
-  const uint32_t *seg;
-  const int32_t *canon_of, *layer_of, *layer_var;
+  float *mf;   // forward messages of each layer's own level (own slots)
+  float *mbc;  // backward messages of each layer's child level (child slots)
+  const uint32_t *garcs;
+  const int4 *grec;
+  const int32_t *canon_of, *layer_of, *layer_var, *root_slot;
   const int32_t *fwd_tiles, *bwd_tiles, *bwd_list, *fwd_big, *bwd_big;
-  const int32_t *root_node, *bdd_canon_off;
+  const int32_t *bdd_canon_off;
   const double *cost;
   const int32_t *var_first, *var_nj;
   float *d_fresh, *mbuf;
   int8_t *xbuf;
-  double *part;
-  long long *ipart;
+  double *part, *lbpart;
   double *lb_hist, *scal;
   float *out0, *out1;
+  int32_t n_bwd_tiles;  // bound partials of big backward tiles start here
 };
 
-// backward message of a child: its value, 0 for the true terminal, +inf for the false terminal
-__device__ __forceinline__ float child_val(const float *__restrict__ mb, int co, uint32_t c) {
-  return c < kTop ? mb[co + int(c)] : (c == kTop ? 0.0f : INFINITY);
+// backward message behind a 2-bit child code of a narrow layer
+__device__ __forceinline__ float c2val(uint32_t code, float2 b) {
+  return code == 0u ? b.x : (code == 1u ? b.y : (code == kC2Top ? 0.0f : INFINITY));
 }
 
-// arc-marginals of one level, minimised per arc label (eqs. "arc-marginal", "marginal-aggregation")
-__device__ __forceinline__ void level_mm_loop(const Dev &D, int no, int w, int co, float lam0, float &m0, float &m1) {
-  for (int u = 0; u < w; ++u) {
-    const uint32_t a = D.arcs[no + u];
-    const float f = D.mf[no + u];
-    m0 = fminf(m0, f + child_val(D.mb, co, a & 0xFFFFu));
-    m1 = fminf(m1, (f + lam0) + child_val(D.mb, co, a >> 16));
-  }
-}
-
-// forward step of the next level (Alg. "Forward BDD update step"), pushed from this level: the
-// lane owns the whole child level, so the min over in-arcs needs no synchronisation
-__device__ __noinline__ void push_loop(const Dev &D, int no, int w, int co, float lam1) {
-  int wc = 0;
-  for (int u = 0; u < w; ++u) {
-    const uint32_t a = D.arcs[no + u];
-    const uint32_t lo = a & 0xFFFFu, hi = a >> 16;
-    if (lo < kTop) wc = max(wc, int(lo) + 1);
-    if (hi < kTop) wc = max(wc, int(hi) + 1);
-  }
-  for (int q = 0; q < wc; ++q) D.mf[co + q] = INFINITY;
-  for (int u = 0; u < w; ++u) {
-    const uint32_t a = D.arcs[no + u];
-    const uint32_t lo = a & 0xFFFFu, hi = a >> 16;
-    const float f = D.mf[no + u];
-    if (lo < kTop) D.mf[co + int(lo)] = fminf(D.mf[co + int(lo)], f);
-    if (hi < kTop) D.mf[co + int(hi)] = fminf(D.mf[co + int(hi)], f + lam1);
-  }
-}
-
-// backward step of this level (Alg. "Backward BDD update step") with the updated multiplier
-__device__ __noinline__ void bwd_step_loop(const Dev &D, int no, int w, int co, float lam1) {
-  for (int u = 0; u < w; ++u) {
-    const uint32_t a = D.arcs[no + u];
-    D.mb[no + u] = fminf(child_val(D.mb, co, a & 0xFFFFu), child_val(D.mb, co, a >> 16) + lam1);
-  }
+// backward message behind a 16-bit child code of a general layer
+__device__ __forceinline__ float c16val(const float *__restrict__ mb, int cs, uint32_t c) {
+  return c < kTop ? mb[cs + int(c)] : (c == kTop ? 0.0f : INFINITY);
 }
 
 // multiplier update of eq. "mma-update"; rows forcing the variable (infinite difference) absorb
@@ -94,53 +68,154 @@ __device__ __forceinline__ float updated(float lam0, float d, float share, int n
   return nf == 0 ? (lam0 - d) + share : (isinf(d) ? lam0 + share : lam0 - d);
 }
 
+// One layer's work split around the J_i sum: begin() computes the min-marginals, push() /
+// bstep() apply the new multiplier in the forward push or the backward step.
+//
+// Every load of a layer is at its own index: its meta word, multiplier, the forward messages of its
+// level (written there by its parent's push) and the backward messages of its child level (written
+// there by its child's backward step), so all of them issue together. Only the stores scatter:
+// the forward push goes to the child layer's own slots, the backward step to the parent layer's
+// child slots. tgt is that child (forward) or parent (backward) layer, -1 at a row's end.
+template <int DIR>
+struct Layer {
+  int L;
+  int tgt;
+  uint32_t meta;
+  float lam0;
+  float2 f, b;     // narrow: own forward messages, child backward messages
+  int4 g;          // general: own slot, own width, child slot, child width
+  float m0, m1;
+
+  __device__ __forceinline__ bool narrow() const { return ((meta >> kMetaWidthShift) & 3u) != 0u; }
+
+  __device__ __forceinline__ void begin(const Dev &D, int L_) {
+    L = L_;
+    meta = D.meta[L];
+    lam0 = D.lam[L];
+    tgt = DIR == kFwd ? D.child[L] : D.parent[L];
+    f = reinterpret_cast<const float2 *>(D.mf)[L];
+    b = reinterpret_cast<const float2 *>(D.mbc)[L];
+    m0 = INFINITY;
+    m1 = INFINITY;
+    if (narrow()) {
+      // arc-marginals (m_fwd + theta) + m_bwd minimised per arc label (eqs. "arc-marginal",
+      // "marginal-aggregation"); a padding node's arcs both lead to BOT
+      const uint32_t lo0 = meta & 3u, hi0 = (meta >> 2) & 3u, lo1 = (meta >> 4) & 3u, hi1 = (meta >> 6) & 3u;
+      m0 = fminf(f.x + c2val(lo0, b), f.y + c2val(lo1, b));
+      m1 = fminf((f.x + lam0) + c2val(hi0, b), (f.y + lam0) + c2val(hi1, b));
+    } else {
+      g = D.grec[L];
+      for (int u = 0; u < g.y; ++u) {
+        const uint32_t a = D.garcs[g.x + u];
+        const float fu = D.mf[g.x + u];
+        m0 = fminf(m0, fu + c16val(D.mbc, g.z, a & 0xFFFFu));
+        m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, g.z, a >> 16));
+      }
+    }
+  }
+
+  // forward step of the next level (Alg. "Forward BDD update step") pushed from this level: the
+  // lane owns the whole next level, so the min over in-arcs needs no synchronisation
+  __device__ __forceinline__ void push(const Dev &D, float lam1) const {
+    if (tgt < 0) return;
+    if (narrow()) {
+      // arc values into the next level's node 0 and node 1, selected per child code (no indexing)
+      const float a0 = f.x, a1 = f.x + lam1, a2 = f.y, a3 = f.y + lam1;
+      const uint32_t k0 = meta & 3u, k1 = (meta >> 2) & 3u, k2 = (meta >> 4) & 3u, k3 = (meta >> 6) & 3u;
+      const float c0 = fminf(fminf(k0 == 0u ? a0 : INFINITY, k1 == 0u ? a1 : INFINITY),
+                             fminf(k2 == 0u ? a2 : INFINITY, k3 == 0u ? a3 : INFINITY));
+      const float c1 = fminf(fminf(k0 == 1u ? a0 : INFINITY, k1 == 1u ? a1 : INFINITY),
+                             fminf(k2 == 1u ? a2 : INFINITY, k3 == 1u ? a3 : INFINITY));
+      reinterpret_cast<float2 *>(D.mf)[tgt] = make_float2(c0, c1);
+    } else {
+      const int cs = D.grec[tgt].x;  // the child layer's own slots
+      for (int q = 0; q < g.w; ++q) D.mf[cs + q] = INFINITY;
+      for (int u = 0; u < g.y; ++u) {
+        const uint32_t a = D.garcs[g.x + u];
+        const uint32_t lo = a & 0xFFFFu, hi = a >> 16;
+        const float fu = D.mf[g.x + u];
+        if (lo < kTop) D.mf[cs + int(lo)] = fminf(D.mf[cs + int(lo)], fu);
+        if (hi < kTop) D.mf[cs + int(hi)] = fminf(D.mf[cs + int(hi)], fu + lam1);
+      }
+    }
+  }
+
+  // backward step of this level (Alg. "Backward BDD update step") with the updated multiplier,
+  // stored at the parent layer's child slots; returns the root's new backward message (E^j) on a
+  // root level, else 0
+  __device__ __forceinline__ double bstep(const Dev &D, float lam1) const {
+    float r;
+    if (narrow()) {
+      const float n0 = fminf(c2val(meta & 3u, b), c2val((meta >> 2) & 3u, b) + lam1);
+      const float n1 = fminf(c2val((meta >> 4) & 3u, b), c2val((meta >> 6) & 3u, b) + lam1);
+      if (tgt >= 0) reinterpret_cast<float2 *>(D.mbc)[tgt] = make_float2(n0, n1);
+      r = n0;
+    } else {
+      r = 0.0f;
+      const int ps = tgt >= 0 ? D.grec[tgt].z : -1;  // the parent layer's child slots
+      for (int u = 0; u < g.y; ++u) {
+        const uint32_t a = D.garcs[g.x + u];
+        const float v = fminf(c16val(D.mbc, g.z, a & 0xFFFFu), c16val(D.mbc, g.z, a >> 16) + lam1);
+        if (ps >= 0) D.mbc[ps + u] = v;
+        if (u == 0) r = v;
+      }
+    }
+    return (meta & kMetaRootBit) ? double(r) : 0.0;
+  }
+};
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8, each XCD
+// with its own L2). Remap so that XCD x takes one contiguous run of the launch's tiles: lines at a
+// boundary between neighbouring tiles are then shared inside one L2 instead of across XCDs.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + min(x, r) + k;
+}
+
+// Sum of one double per lane over the workgroup in a fixed shape (butterfly inside each
+// wavefront, then the wavefront totals in order), so the result does not depend on timing.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = int(threadIdx.x) >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = int(blockDim.x) >> 6;
+  for (int q = 0; q < nw; ++q) s += sh[q];
+  __syncthreads();
+  return s;
+}
+
 template <int DIR, int MODE>
 __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0, const int use_list) {
   __shared__ float s_d[kTile];
   __shared__ float s_share[kTile];
   __shared__ int s_nf[kTile];
+  __shared__ double s_red[kTile / 64];
   const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
-  const int tix = tile0 + int(blockIdx.x);
+  const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
   const int p0 = tiles[2 * tix];
-  const int cnt = tiles[2 * tix + 1] - p0;
+  // a backward tile's end carries bit 31 when the tile holds a root level
+  const uint32_t end = uint32_t(tiles[2 * tix + 1]);
+  const bool roots = DIR == kBwd && (end & kTileRootBit) != 0u;
+  const int cnt = int(end & ~kTileRootBit) - p0;
   const int s = int(threadIdx.x);
   const bool active = s < cnt;
 
-  int L = 0, no = 0, w = 0, co = -1;
-  float lam0 = 0.0f;
-  uint32_t sg = 0;
-  uint32_t ar[4] = {kBot, kBot, kBot, kBot};
-  float f[4] = {0.f, 0.f, 0.f, 0.f}, b0[4] = {0.f, 0.f, 0.f, 0.f}, b1[4] = {0.f, 0.f, 0.f, 0.f};
-  float m0 = INFINITY, m1 = INFINITY;
-  if (active) {
-    L = (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s;
-    no = D.node_off[L];
-    w = D.node_off[L + 1] - no;
-    co = D.child_off[L];
-    lam0 = D.lam[L];
-    if (MODE == kUpdate) sg = D.seg[L];
-    if (w <= 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < w) {
-          ar[u] = D.arcs[no + u];
-          f[u] = D.mf[no + u];
-          b0[u] = child_val(D.mb, co, ar[u] & 0xFFFFu);
-          b1[u] = child_val(D.mb, co, ar[u] >> 16);
-          m0 = fminf(m0, f[u] + b0[u]);
-          m1 = fminf(m1, (f[u] + lam0) + b1[u]);
-        }
-      }
-    } else {
-      level_mm_loop(D, no, w, co, lam0, m0, m1);
-    }
-  }
-  const float d = m1 - m0;
-  float lam1 = lam0;
+  Layer<DIR> ly;
+  ly.meta = 0;
+  ly.lam0 = 0.0f;
+  ly.m0 = ly.m1 = 0.0f;
+  if (active) ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+  const float d = ly.m1 - ly.m0;
+  float lam1 = ly.lam0;
   if (MODE == kUpdate) {
     s_d[s] = d;
     __syncthreads();
-    const int pos = int(sg & 0xFFFFu), len = int(sg >> 16);
+    const int pos = int((ly.meta >> kMetaPosShift) & kMetaField);
+    const int len = int((ly.meta >> kMetaLenShift) & kMetaField);
     if (active && pos == 0) {
       // J_i sum in ascending row order (the segment is sorted by row)
       float sum = 0.0f;
@@ -156,62 +231,28 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     __syncthreads();
     if (active) {
       const int h = s - pos;
-      lam1 = updated(lam0, d, s_share[h], s_nf[h]);
-      D.lam[L] = lam1;
+      lam1 = updated(ly.lam0, d, s_share[h], s_nf[h]);
+      D.lam[ly.L] = lam1;
     }
   }
-  if (!active) return;
-  if (MODE == kExtract) {
-    const int c = D.canon_of[L];
-    if (D.out0) D.out0[c] = m0;
-    if (D.out1) D.out1[c] = m1;
-    D.d_fresh[L] = d;
+  if (MODE == kExtract && active) {
+    const int c = D.canon_of[ly.L];
+    if (D.out0) D.out0[c] = ly.m0;
+    if (D.out1) D.out1[c] = ly.m1;
+    D.d_fresh[ly.L] = d;
   }
   if (DIR == kFwd) {
-    if (co < 0) return;
-    if (w <= 4) {
-      float c[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-      int wc = 0;
-      bool fits = true;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < w) {
-          const uint32_t lo = ar[u] & 0xFFFFu, hi = ar[u] >> 16;
-          const float v0 = f[u], v1 = f[u] + lam1;
-          if (lo < kTop) {
-            wc = max(wc, int(lo) + 1);
-            fits = fits && lo < 4u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (lo == uint32_t(q)) c[q] = fminf(c[q], v0);
-          }
-          if (hi < kTop) {
-            wc = max(wc, int(hi) + 1);
-            fits = fits && hi < 4u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (hi == uint32_t(q)) c[q] = fminf(c[q], v1);
-          }
-        }
-      }
-      if (fits) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q < wc) D.mf[co + q] = c[q];
-      } else {
-        push_loop(D, no, w, co, lam1);
-      }
-    } else {
-      push_loop(D, no, w, co, lam1);
-    }
+    if (active) ly.push(D, lam1);
   } else {
-    if (w <= 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < w) D.mb[no + u] = fminf(b0[u], b1[u] + lam1);
-    } else {
-      bwd_step_loop(D, no, w, co, lam1);
+    const double e = active ? ly.bstep(D, lam1) : 0.0;
+    // bound partial per wavefront: a fixed butterfly, only in tiles holding root levels (the
+    // branch is uniform over the workgroup)
+    double v = 0.0;
+    if (roots) {
+      v = e;
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     }
+    if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
   }
 }
 
@@ -221,21 +262,20 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
   __shared__ float s_d[kBigMax];
   __shared__ float s_share;
   __shared__ int s_nf;
+  __shared__ double s_red[kTile / 64];
   const int32_t *big = DIR == kFwd ? D.fwd_big : D.bwd_big;
   const int b = big0 + int(blockIdx.x);
   const int p0 = big[2 * b];
   const int cnt = big[2 * b + 1] - p0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    const int L = (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s;
-    const int no = D.node_off[L], w = D.node_off[L + 1] - no, co = D.child_off[L];
-    float m0 = INFINITY, m1 = INFINITY;
-    level_mm_loop(D, no, w, co, D.lam[L], m0, m1);
-    s_d[s] = m1 - m0;
+    Layer<DIR> ly;
+    ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+    s_d[s] = ly.m1 - ly.m0;
     if (MODE == kExtract) {
-      const int c = D.canon_of[L];
-      if (D.out0) D.out0[c] = m0;
-      if (D.out1) D.out1[c] = m1;
-      D.d_fresh[L] = m1 - m0;
+      const int c = D.canon_of[ly.L];
+      if (D.out0) D.out0[c] = ly.m0;
+      if (D.out1) D.out1[c] = ly.m1;
+      D.d_fresh[ly.L] = ly.m1 - ly.m0;
     }
   }
   if (MODE == kUpdate) {
@@ -252,20 +292,27 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
     }
     __syncthreads();
   }
+  double e = 0.0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    const int L = (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s;
-    const int no = D.node_off[L], w = D.node_off[L + 1] - no, co = D.child_off[L];
-    float lam1 = D.lam[L];
+    Layer<DIR> ly;
+    ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+    float lam1 = ly.lam0;
     if (MODE == kUpdate) {
       lam1 = updated(lam1, s_d[s], s_share, s_nf);
-      D.lam[L] = lam1;
+      D.lam[ly.L] = lam1;
     }
-    if (DIR == kFwd) {
-      if (co >= 0) push_loop(D, no, w, co, lam1);
-    } else {
-      bwd_step_loop(D, no, w, co, lam1);
-    }
+    if (DIR == kFwd) ly.push(D, lam1);
+    else e += ly.bstep(D, lam1);
   }
+  if (DIR == kBwd) {
+    const double t = block_sum(e, s_red);
+    if (threadIdx.x == 0) D.lbpart[kTile / 64 * D.n_bwd_tiles + b] = t;
+  }
+}
+
+__global__ void fill_kernel(float *p, float v, int n) {
+  const int i = int(blockIdx.x) * blockDim.x + int(threadIdx.x);
+  if (i < n) p[i] = v;
 }
 
 __global__ void init_lambda_kernel(const Dev D, int I) {
@@ -278,7 +325,7 @@ __global__ void init_lambda_kernel(const Dev D, int I) {
 __global__ void root_zero_kernel(const Dev D, int m) {
   const int j = int(blockIdx.x) * blockDim.x + int(threadIdx.x);
   if (j >= m) return;
-  const int r = D.root_node[j];
+  const int r = D.root_slot[j];
   if (r >= 0) D.mf[r] = 0.0f;
 }
 
@@ -292,62 +339,29 @@ __global__ void lambda_in_kernel(const Dev D, const float *in, int I) {
   if (L < I) D.lam[L] = in[D.canon_of[L]];
 }
 
-// fixed-shape block tree sum of 256 doubles
-__device__ __forceinline__ double block_sum256(double v, double *sh) {
-  const int t = int(threadIdx.x);
-  sh[t] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ double block_max256(double v, double *sh) {
-  const int t = int(threadIdx.x);
-  sh[t] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-// LB = sum_j E^j, E^j = backward message of the root (problem (D)); fixed partition and tree
-__global__ __launch_bounds__(256) void lb_partial_kernel(const Dev D, int m) {
-  __shared__ double sh[256];
-  const int chunk = (m + kLbBlocks - 1) / kLbBlocks;
-  const int j0 = int(blockIdx.x) * chunk, j1 = min(m, j0 + chunk);
+// LB = sum_j E^j (problem (D)) from the per-tile partials of the backward sweep: kLbStage blocks
+// each sum one fixed contiguous chunk, then one block sums the chunk totals; fixed order throughout
+constexpr int kLbStage = 256;
+__global__ __launch_bounds__(256) void lb_stage_kernel(const Dev D, int nparts) {
+  __shared__ double sh[4];
+  const int chunk = (nparts + kLbStage - 1) / kLbStage;
+  const int q0 = int(blockIdx.x) * chunk, q1 = min(nparts, q0 + chunk);
   double acc = 0.0;
-  for (int j = j0 + int(threadIdx.x); j < j1; j += 256) {
-    const int r = D.root_node[j];
-    if (r >= 0) acc += double(D.mb[r]);
-  }
-  const double s = block_sum256(acc, sh);
+  for (int q = q0 + int(threadIdx.x); q < q1; q += 256) acc += D.lbpart[q];
+  const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) D.part[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kLbBlocks) void lb_final_kernel(const Dev D, double lb_const, int slot) {
-  __shared__ double sh[kLbBlocks];
-  const int t = int(threadIdx.x);
-  sh[t] = D.part[t];
-  __syncthreads();
-  for (int s = kLbBlocks / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  if (t == 0) D.lb_hist[slot] = sh[0] + lb_const;
+__global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, double lb_const, int slot) {
+  __shared__ double sh[kLbStage / 64];
+  const double s = block_sum(D.part[threadIdx.x], sh);
+  if (threadIdx.x == 0) D.lb_hist[slot] = s + lb_const;
 }
 
 // per variable: g_i = c_i - sum_j lambda^j_i; partial max |g| and sum of min(0, g)
 __global__ __launch_bounds__(256) void residual_partial_kernel(const Dev D, int n) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
+  __shared__ double smax[256];
   const int chunk = (n + kLbBlocks - 1) / kLbBlocks;
   const int i0 = int(blockIdx.x) * chunk, i1 = min(n, i0 + chunk);
   double mx = 0.0, corr = 0.0;
@@ -361,36 +375,39 @@ __global__ __launch_bounds__(256) void residual_partial_kernel(const Dev D, int 
     mx = fmax(mx, fabs(g));
     corr += fmin(0.0, g);
   }
-  const double a = block_max256(mx, sh);
-  const double b = block_sum256(corr, sh);
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const double b = block_sum(corr, sh);
   if (threadIdx.x == 0) {
-    D.part[blockIdx.x] = a;
+    D.part[blockIdx.x] = smax[0];
     D.part[kLbBlocks + blockIdx.x] = b;
   }
 }
 
 __global__ __launch_bounds__(kLbBlocks) void residual_final_kernel(const Dev D) {
-  __shared__ double sa[kLbBlocks], sb[kLbBlocks];
+  __shared__ double sa[kLbBlocks];
+  __shared__ double sh[kLbBlocks / 64];
   const int t = int(threadIdx.x);
   sa[t] = D.part[t];
-  sb[t] = D.part[kLbBlocks + t];
   __syncthreads();
-  for (int s = kLbBlocks / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sa[t] = fmax(sa[t], sa[t + s]);
-      sb[t] += sb[t + s];
-    }
+  for (int st = kLbBlocks / 2; st > 0; st >>= 1) {
+    if (t < st) sa[t] = fmax(sa[t], sa[t + st]);
     __syncthreads();
   }
+  const double b = block_sum(D.part[kLbBlocks + t], sh);
   if (t == 0) {
     D.scal[0] = sa[0];
-    D.scal[1] = sb[0];
+    D.scal[1] = b;
   }
 }
 
 // M_i = sum_j (m1 - m0) in ascending row order (Sec. 4), x_i = [M_i <= 0]; c^T x partials
 __global__ __launch_bounds__(256) void round_var_kernel(const Dev D, int n) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   const int chunk = (n + kLbBlocks - 1) / kLbBlocks;
   const int i0 = int(blockIdx.x) * chunk, i1 = min(n, i0 + chunk);
   double obj = 0.0;
@@ -409,50 +426,44 @@ __global__ __launch_bounds__(256) void round_var_kernel(const Dev D, int n) {
     D.xbuf[i] = x;
     if (x) obj += D.cost[i];
   }
-  const double s = block_sum256(obj, sh);
+  const double s = block_sum(obj, sh);
   if (threadIdx.x == 0) D.part[blockIdx.x] = s;
 }
 
 // a row holds at x iff x's path through its BDD ends in the true terminal (Prop. "Canonicity")
 __global__ __launch_bounds__(256) void violation_kernel(const Dev D, int m) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   const int chunk = (m + kLbBlocks - 1) / kLbBlocks;
   const int j0 = int(blockIdx.x) * chunk, j1 = min(m, j0 + chunk);
   double bad = 0.0;
   for (int j = j0 + int(threadIdx.x); j < j1; j += 256) {
     const int c0 = D.bdd_canon_off[j], c1 = D.bdd_canon_off[j + 1];
-    int cur = 0;
+    int slot = D.root_slot[j];
     for (int c = c0; c < c1; ++c) {
       const int L = D.layer_of[c];
-      const uint32_t a = D.arcs[D.node_off[L] + cur];
+      const uint32_t a = D.garcs[slot];
       const uint32_t ch = D.xbuf[D.layer_var[L]] ? (a >> 16) : (a & 0xFFFFu);
       if (ch == kBot) {
         bad += 1.0;
         break;
       }
-      cur = ch == kTop ? 0 : int(ch);
+      if (ch == kTop) break;
+      const int Lc = D.layer_of[c + 1];
+      slot = (D.grec ? D.grec[Lc].x : 2 * Lc) + int(ch);
     }
   }
-  const double s = block_sum256(bad, sh);
+  const double s = block_sum(bad, sh);
   if (threadIdx.x == 0) D.part[kLbBlocks + blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(kLbBlocks) void round_final_kernel(const Dev D) {
-  __shared__ double sa[kLbBlocks], sb[kLbBlocks];
+  __shared__ double sh[kLbBlocks / 64];
   const int t = int(threadIdx.x);
-  sa[t] = D.part[t];
-  sb[t] = D.part[kLbBlocks + t];
-  __syncthreads();
-  for (int s = kLbBlocks / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sa[t] += sa[t + s];
-      sb[t] += sb[t + s];
-    }
-    __syncthreads();
-  }
+  const double a = block_sum(D.part[t], sh);
+  const double b = block_sum(D.part[kLbBlocks + t], sh);
   if (t == 0) {
-    D.scal[2] = sa[0];
-    D.scal[3] = sb[0];
+    D.scal[2] = a;
+    D.scal[3] = b;
   }
 }
 
@@ -479,9 +490,9 @@ int32_t hip_fail(hipError_t e, const char *what) {
   return set_error(BDDMP_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                 \
-  do {                                      \
-    hipError_t e_ = (expr);                 \
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
@@ -495,7 +506,7 @@ struct EventPair {
   int cls;
 };
 
-// One pass: every wave in order; ev != nullptr records an event pair around each launch.
+// One pass: every wave in order; ev != nullptr records an event pair around each wave's launches.
 template <int DIR, int MODE>
 int32_t run_pass(Solver &S, std::vector<EventPair> *ev, int cls) {
   const Plan &P = *S.plan;
@@ -526,6 +537,7 @@ int32_t run_pass(Solver &S, std::vector<EventPair> *ev, int cls) {
   return BDDMP_OK;
 }
 
+// the bound of the backward sweep just run, from its per-tile partials
 int32_t record_lb(Solver &S, std::vector<EventPair> *ev) {
   const Plan &P = *S.plan;
   EventPair e{};
@@ -535,10 +547,10 @@ int32_t record_lb(Solver &S, std::vector<EventPair> *ev) {
     e.cls = 2;
     HIP_TRY(hipEventRecord(e.a, S.stream), "hipEventRecord");
   }
-  hipLaunchKernelGGL(lb_partial_kernel, dim3(kLbBlocks), dim3(256), 0, S.stream, S.D, P.m);
-  if (int32_t rc = launched("lb_partial")) return rc;
   const int slot = int(S.n_hist % P.hist_cap);
-  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbBlocks), 0, S.stream, S.D, P.lb_const, slot);
+  hipLaunchKernelGGL(lb_stage_kernel, dim3(kLbStage), dim3(256), 0, S.stream, S.D, int(P.n_lbpart));
+  if (int32_t rc = launched("lb_stage")) return rc;
+  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, S.stream, S.D, P.lb_const, slot);
   if (int32_t rc = launched("lb_final")) return rc;
   if (ev) {
     HIP_TRY(hipEventRecord(e.b, S.stream), "hipEventRecord");
@@ -574,22 +586,23 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   const ArenaLayout &A = P.lay;
   char *b = S->arena;
   Dev &D = S->D;
-  D.arcs = reinterpret_cast<const uint32_t *>(b + A.arcs);
-  D.mf = reinterpret_cast<float *>(b + A.mf);
-  D.mb = reinterpret_cast<float *>(b + A.mb);
-  D.node_off = reinterpret_cast<const int32_t *>(b + A.node_off);
-  D.child_off = reinterpret_cast<const int32_t *>(b + A.child_off);
+  D.meta = reinterpret_cast<const uint32_t *>(b + A.meta);
+  D.child = reinterpret_cast<const int32_t *>(b + A.child);
+  D.parent = reinterpret_cast<const int32_t *>(b + A.parent);
   D.lam = reinterpret_cast<float *>(b + A.lam);
-  D.seg = reinterpret_cast<const uint32_t *>(b + A.seg);
+  D.mf = reinterpret_cast<float *>(b + A.mf);
+  D.mbc = reinterpret_cast<float *>(b + A.mbc);
+  D.garcs = reinterpret_cast<const uint32_t *>(b + A.garcs);
+  D.grec = P.grec.empty() ? nullptr : reinterpret_cast<const int4 *>(b + A.grec);
   D.canon_of = reinterpret_cast<const int32_t *>(b + A.canon_of);
   D.layer_of = reinterpret_cast<const int32_t *>(b + A.layer_of);
   D.layer_var = reinterpret_cast<const int32_t *>(b + A.layer_var);
+  D.root_slot = reinterpret_cast<const int32_t *>(b + A.root_slot);
   D.fwd_tiles = reinterpret_cast<const int32_t *>(b + A.fwd_tiles);
   D.bwd_tiles = reinterpret_cast<const int32_t *>(b + A.bwd_tiles);
   D.bwd_list = reinterpret_cast<const int32_t *>(b + A.bwd_list);
   D.fwd_big = reinterpret_cast<const int32_t *>(b + A.fwd_big);
   D.bwd_big = reinterpret_cast<const int32_t *>(b + A.bwd_big);
-  D.root_node = reinterpret_cast<const int32_t *>(b + A.root_node);
   D.bdd_canon_off = reinterpret_cast<const int32_t *>(b + A.bdd_canon_off);
   D.cost = reinterpret_cast<const double *>(b + A.cost);
   D.var_first = reinterpret_cast<const int32_t *>(b + A.var_first);
@@ -598,29 +611,31 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.mbuf = reinterpret_cast<float *>(b + A.mbuf);
   D.xbuf = reinterpret_cast<int8_t *>(b + A.xbuf);
   D.part = reinterpret_cast<double *>(b + A.part);
-  D.ipart = reinterpret_cast<long long *>(b + A.ipart);
+  D.lbpart = reinterpret_cast<double *>(b + A.lbpart);
   D.lb_hist = reinterpret_cast<double *>(b + A.lb_hist);
   D.scal = reinterpret_cast<double *>(b + A.scal);
   D.out0 = D.out1 = nullptr;
+  D.n_bwd_tiles = int32_t(P.bwd_tiles.size() / 2);
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
     if (!nbytes) return hipSuccess;
     return hipMemcpyAsync(b + off, src, nbytes, hipMemcpyHostToDevice, S->stream);
   };
   const hipError_t errs[] = {
-      up(A.arcs, P.arcs.data(), 4 * P.arcs.size()),
-      up(A.node_off, P.node_off.data(), 4 * P.node_off.size()),
-      up(A.child_off, P.child_off.data(), 4 * P.child_off.size()),
-      up(A.seg, P.seg.data(), 4 * P.seg.size()),
+      up(A.meta, P.meta.data(), 4 * P.meta.size()),
+      up(A.child, P.child.data(), 4 * P.child.size()),
+      up(A.parent, P.parent.data(), 4 * P.parent.size()),
+      up(A.garcs, P.garcs.data(), 4 * P.garcs.size()),
+      up(A.grec, P.grec.data(), 4 * P.grec.size()),
       up(A.canon_of, P.canon_of.data(), 4 * P.canon_of.size()),
       up(A.layer_of, P.layer_of.data(), 4 * P.layer_of.size()),
       up(A.layer_var, P.layer_var.data(), 4 * P.layer_var.size()),
+      up(A.root_slot, P.root_slot.data(), 4 * P.root_slot.size()),
       up(A.fwd_tiles, P.fwd_tiles.data(), 4 * P.fwd_tiles.size()),
       up(A.bwd_tiles, P.bwd_tiles.data(), 4 * P.bwd_tiles.size()),
       up(A.bwd_list, P.bwd_list.data(), 4 * P.bwd_list.size()),
       up(A.fwd_big, P.fwd_big.data(), 4 * P.fwd_big.size()),
       up(A.bwd_big, P.bwd_big.data(), 4 * P.bwd_big.size()),
-      up(A.root_node, P.root_node.data(), 4 * P.root_node.size()),
       up(A.bdd_canon_off, P.bdd_canon_off.data(), 4 * P.bdd_canon_off.size()),
       up(A.cost, P.cost.data(), 8 * P.cost.size()),
       up(A.var_first, P.var_first.data(), 4 * P.var_first.size()),
@@ -639,10 +654,17 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   return BDDMP_OK;
 }
 
-// Initialisation of Alg. "Min-marginal averaging": lambda^j_i = c_i / |J_i|, forward messages of
-// the roots = 0, and the initial backward sweep that fills every backward message.
+// Initialisation of Alg. "Min-marginal averaging": lambda^j_i = c_i / |J_i|, forward messages
+// +inf except the roots (0; padding slots stay +inf), and the initial backward sweep that fills
+// every backward message.
 int32_t solver_reset(Solver &S) {
   const Plan &P = *S.plan;
+  const int nslots = int(P.S + 4);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(nslots, 256)), dim3(256), 0, S.stream, S.D.mf, INFINITY, nslots);
+  if (int32_t rc = launched("fill")) return rc;
+  const int ncslots = int(P.Sc + 4);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(ncslots, 256)), dim3(256), 0, S.stream, S.D.mbc, INFINITY, ncslots);
+  if (int32_t rc = launched("fill")) return rc;
   if (P.I > 0) {
     hipLaunchKernelGGL(init_lambda_kernel, dim3(blocks_for(P.I, 256)), dim3(256), 0, S.stream, S.D, int(P.I));
     if (int32_t rc = launched("init_lambda")) return rc;
@@ -669,14 +691,12 @@ int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_
   double h = 0.0, sc[2] = {0.0, 0.0};
   const int slot = int((S.n_hist - 1) % P.hist_cap);
   HIP_TRY(hipMemcpyAsync(&h, S.D.lb_hist + slot, 8, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
-  if (residual || any_lambda_bound) {
-    if (P.n > 0) {
-      hipLaunchKernelGGL(residual_partial_kernel, dim3(kLbBlocks), dim3(256), 0, S.stream, S.D, P.n);
-      if (int32_t rc = launched("residual_partial")) return rc;
-      hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(kLbBlocks), 0, S.stream, S.D);
-      if (int32_t rc = launched("residual_final")) return rc;
-      HIP_TRY(hipMemcpyAsync(sc, S.D.scal, 16, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
-    }
+  if ((residual || any_lambda_bound) && P.n > 0) {
+    hipLaunchKernelGGL(residual_partial_kernel, dim3(kLbBlocks), dim3(256), 0, S.stream, S.D, P.n);
+    if (int32_t rc = launched("residual_partial")) return rc;
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(kLbBlocks), 0, S.stream, S.D);
+    if (int32_t rc = launched("residual_final")) return rc;
+    HIP_TRY(hipMemcpyAsync(sc, S.D.scal, 16, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
   if (lb) *lb = h;
@@ -773,9 +793,16 @@ int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
   for (const EventPair &e : ev) {
     float ms = 0.0f;
     if (!rc && se == hipSuccess) hipEventElapsedTime(&ms, e.a, e.b);
-    if (e.cls == 0) { r.fwd_ms += ms; r.fwd_launches++; }
-    else if (e.cls == 1) { r.bwd_ms += ms; r.bwd_launches++; }
-    else { r.lb_ms += ms; r.lb_launches++; }
+    if (e.cls == 0) {
+      r.fwd_ms += ms;
+      r.fwd_launches++;
+    } else if (e.cls == 1) {
+      r.bwd_ms += ms;
+      r.bwd_launches++;
+    } else {
+      r.lb_ms += ms;
+      r.lb_launches++;
+    }
     hipEventDestroy(e.a);
     hipEventDestroy(e.b);
   }

@@ -38,6 +38,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["paper_2009_00481_amd/csrc/solver.hip", "paper_2009_00481_amd/csrc/plan.cpp",
+                  "paper_2009_00481_amd/csrc/internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per launch of the wave kernels from the committed counter summary, or None when the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"wave_kernels_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic source_hash="):
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if kv.get("source_hash") != kernel_source_hash():
+                return None
+            return {"fwd": float(kv["fwd_bytes_per_launch"]), "bwd": float(kv["bwd_bytes_per_launch"])}
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,8 +164,11 @@ def main():
     else:
         kname, kms, kb, kl = "wave_kernel<bwd,update>", kt["bwd_ms"], kt["bwd_bytes"], kt["bwd_launches"]
     achieved = (kb / kl) / ((kms / kl) * 1e-3) / 1e9
+    tr = committed_traffic(args.workload)
+    traffic = None if tr is None else tr["fwd" if "fwd" in kname else "bwd"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+                "kernel": kname,
                 "bytes_per_launch": kb / kl, "avg_launch_us": kms / kl * 1e3,
                 "both_passes_gbs": round((kt["fwd_bytes"] + kt["bwd_bytes"]) / ((kt["fwd_ms"] + kt["bwd_ms"]) * 1e-3) / 1e9, 1)}
 

@@ -69,6 +69,7 @@ struct WaveRange {
   int32_t tile_begin, tile_end;  // normal tiles [begin, end) in the pass's tile list
   int32_t big_begin, big_end;    // big tiles (one variable with more than kTile rows)
   int32_t list;                  // backward pass: 1 if positions go through bwd_list
+  bool narrow_only;              // every layer of the wave is narrow
   int64_t nodes, layers;         // work of the wave (for the byte model)
 };
 

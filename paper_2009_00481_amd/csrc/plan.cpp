@@ -178,6 +178,7 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
               continue;
             }
             const uint32_t meta = P.meta[L];
+            if (wr.narrow_only && ((meta >> kMetaWidthShift) & 3u) == 0u) return "narrow-only wave holds a wide level";
             const int64_t head = p - int64_t((meta >> kMetaPosShift) & kMetaField);
             if (nj > kTile || head < p0 || head + nj > p1) return "segment leaves its tile";
           }
@@ -491,10 +492,13 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   auto wave_work = [&](const std::vector<int32_t> &vars, WaveRange &wr) {
     wr.nodes = 0;
     wr.layers = 0;
+    wr.narrow_only = true;
     for (int32_t i : vars)
       for (int32_t q = 0; q < P.var_nj[i]; ++q) {
-        wr.nodes += ownw[P.var_first[i] + q];
+        const int32_t Lq = P.var_first[i] + q;
+        wr.nodes += ownw[Lq];
         wr.layers += 1;
+        wr.narrow_only = wr.narrow_only && ((P.meta[Lq] >> kMetaWidthShift) & 3u) != 0u;
       }
   };
   for (int32_t t = 1; t <= P.Df; ++t) {

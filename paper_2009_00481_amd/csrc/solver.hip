@@ -54,7 +54,10 @@ struct Dev {
 
 // backward message behind a 2-bit child code of a narrow layer
 __device__ __forceinline__ float c2val(uint32_t code, float2 b) {
-  return code == 0u ? b.x : (code == 1u ? b.y : (code == kC2Top ? 0.0f : INFINITY));
+  // codes 0, 1: node of the next level; 2 (kC2Bot): +inf; 3 (kC2Top): 0. Selects, no branches.
+  const float node = (code & 1u) ? b.y : b.x;
+  const float term = (code & 1u) ? 0.0f : INFINITY;
+  return (code & 2u) ? term : node;
 }
 
 // backward message behind a 16-bit child code of a general layer
@@ -76,7 +79,9 @@ __device__ __forceinline__ float updated(float lam0, float d, float share, int n
 // there by its child's backward step), so all of them issue together. Only the stores scatter:
 // the forward push goes to the child layer's own slots, the backward step to the parent layer's
 // child slots. tgt is that child (forward) or parent (backward) layer, -1 at a row's end.
-template <int DIR>
+// NARROW_ONLY instantiations serve waves without wide levels: no per-lane branch, so the compiler
+// issues all loads at once instead of sinking the message loads behind the meta word.
+template <int DIR, bool NARROW_ONLY>
 struct Layer {
   int L;
   int tgt;
@@ -86,7 +91,9 @@ struct Layer {
   int4 g;          // general: own slot, own width, child slot, child width
   float m0, m1;
 
-  __device__ __forceinline__ bool narrow() const { return ((meta >> kMetaWidthShift) & 3u) != 0u; }
+  __device__ __forceinline__ bool narrow() const {
+    return NARROW_ONLY || ((meta >> kMetaWidthShift) & 3u) != 0u;
+  }
 
   __device__ __forceinline__ void begin(const Dev &D, int L_) {
     L = L_;
@@ -95,6 +102,8 @@ struct Layer {
     tgt = DIR == kFwd ? D.child[L] : D.parent[L];
     f = reinterpret_cast<const float2 *>(D.mf)[L];
     b = reinterpret_cast<const float2 *>(D.mbc)[L];
+    // keep the five independent loads ahead of every use, so they are in flight together
+    __builtin_amdgcn_sched_barrier(0);
     m0 = INFINITY;
     m1 = INFINITY;
     if (narrow()) {
@@ -188,8 +197,9 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return s;
 }
 
-template <int DIR, int MODE>
-__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0, const int use_list) {
+// LIST: backward positions go through bwd_list (a wave that is not one contiguous layer range).
+template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
+__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0) {
   __shared__ float s_d[kTile];
   __shared__ float s_share[kTile];
   __shared__ int s_nf[kTile];
@@ -204,11 +214,11 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   const int s = int(threadIdx.x);
   const bool active = s < cnt;
 
-  Layer<DIR> ly;
+  Layer<DIR, NARROW_ONLY> ly;
   ly.meta = 0;
   ly.lam0 = 0.0f;
   ly.m0 = ly.m1 = 0.0f;
-  if (active) ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+  if (active) ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
   const float d = ly.m1 - ly.m0;
   float lam1 = ly.lam0;
   if (MODE == kUpdate) {
@@ -257,8 +267,8 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
 }
 
 // One variable with more than kTile rows per workgroup (its layers are the whole tile).
-template <int DIR, int MODE>
-__global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int big0, const int use_list) {
+template <int DIR, int MODE, bool LIST>
+__global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int big0) {
   __shared__ float s_d[kBigMax];
   __shared__ float s_share;
   __shared__ int s_nf;
@@ -268,8 +278,8 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
   const int p0 = big[2 * b];
   const int cnt = big[2 * b + 1] - p0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    Layer<DIR> ly;
-    ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+    Layer<DIR, false> ly;
+    ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
     s_d[s] = ly.m1 - ly.m0;
     if (MODE == kExtract) {
       const int c = D.canon_of[ly.L];
@@ -294,8 +304,8 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
   }
   double e = 0.0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    Layer<DIR> ly;
-    ly.begin(D, (DIR == kBwd && use_list) ? D.bwd_list[p0 + s] : p0 + s);
+    Layer<DIR, false> ly;
+    ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
     float lam1 = ly.lam0;
     if (MODE == kUpdate) {
       lam1 = updated(lam1, s_d[s], s_share, s_nf);
@@ -522,11 +532,22 @@ int32_t run_pass(Solver &S, std::vector<EventPair> *ev, int cls) {
       HIP_TRY(hipEventRecord(e.a, S.stream), "hipEventRecord");
     }
     if (nt > 0) {
-      hipLaunchKernelGGL((wave_kernel<DIR, MODE>), dim3(nt), dim3(kTile), 0, S.stream, S.D, wr.tile_begin, wr.list);
+      const bool list = DIR == kBwd && wr.list;
+      if (wr.narrow_only && !list)
+        hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, false>), dim3(nt), dim3(kTile), 0, S.stream, S.D, wr.tile_begin);
+      else if (wr.narrow_only)
+        hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, true>), dim3(nt), dim3(kTile), 0, S.stream, S.D, wr.tile_begin);
+      else if (!list)
+        hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, false>), dim3(nt), dim3(kTile), 0, S.stream, S.D, wr.tile_begin);
+      else
+        hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, true>), dim3(nt), dim3(kTile), 0, S.stream, S.D, wr.tile_begin);
       if (int32_t rc = launched("wave kernel")) return rc;
     }
     if (nb > 0) {
-      hipLaunchKernelGGL((wave_big_kernel<DIR, MODE>), dim3(nb), dim3(kTile), 0, S.stream, S.D, wr.big_begin, wr.list);
+      if (DIR == kBwd && wr.list)
+        hipLaunchKernelGGL((wave_big_kernel<DIR, MODE, true>), dim3(nb), dim3(kTile), 0, S.stream, S.D, wr.big_begin);
+      else
+        hipLaunchKernelGGL((wave_big_kernel<DIR, MODE, false>), dim3(nb), dim3(kTile), 0, S.stream, S.D, wr.big_begin);
       if (int32_t rc = launched("wave kernel (big)")) return rc;
     }
     if (ev) {

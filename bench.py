@@ -38,8 +38,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ["paper_2009_00481_amd/csrc/solver.hip", "paper_2009_00481_amd/csrc/plan.cpp",
-                  "paper_2009_00481_amd/csrc/internal.h"]
+KERNEL_SOURCES = ["paper_2009_00481_amd/csrc/kernels.hip", "paper_2009_00481_amd/csrc/kernels.h",
+                  "paper_2009_00481_amd/csrc/plan.cpp", "paper_2009_00481_amd/csrc/internal.h"]
 
 
 def kernel_source_hash() -> str:
@@ -136,7 +136,7 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # per-launch kernel times (HIP events on the solver's stream) for the roofline
+    # pass times (HIP events around each whole pass, on the solver's stream) for the roofline
     kt = s.time_kernels(args.profile_iters)
     log(f"[bench] kernel times over {args.profile_iters} iterations: {kt}")
 

@@ -86,10 +86,10 @@ typedef struct {
 } bddmp_stats;
 
 typedef struct {
-  double fwd_ms, bwd_ms, lb_ms;          /* summed kernel time per class over the timed iterations */
+  double fwd_ms, bwd_ms, lb_ms;          /* summed pass time per class over the timed iterations   */
   int64_t fwd_launches, bwd_launches, lb_launches;
   double fwd_bytes, bwd_bytes;           /* algorithmic bytes moved by all launches of the class   */
-  double iter_ms;                        /* event time per iteration without per-launch events     */
+  double iter_ms;                        /* event time per iteration without inner events          */
 } bddmp_kernel_times;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -208,11 +208,12 @@ int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
 int32_t bddmp_solver_round_primal(bddmp_solver *s, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated);
 
 /*
- * Diagnostics: runs n_iters iterations with a HIP event pair around every wave launch and reports
- * summed kernel times per class with the algorithmic bytes of those launches (forward and backward
- * passes move 20 bytes per node and 8 per incidence: arcs 8, messages 12, multiplier 8), then the
- * same number of iterations without per-launch events for iter_ms. The solver advances by
- * 2*n_iters iterations. Synchronises.
+ * Diagnostics: runs n_iters iterations with a HIP event pair around each forward pass, each
+ * backward pass and each bound reduction (not around single launches, so the events add no gap
+ * between the waves of a pass) and reports the summed times per class, the launches they cover
+ * (one per wave) and the algorithmic bytes of those passes (20 bytes per node and 8 per incidence:
+ * arcs 8, messages 12, multiplier 8); then the same number of iterations without events for
+ * iter_ms. The solver advances by 2*n_iters iterations. Synchronises.
  */
 int32_t bddmp_solver_time_kernels(bddmp_solver *s, int32_t n_iters, bddmp_kernel_times *out);
 

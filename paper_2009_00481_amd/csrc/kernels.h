@@ -1,0 +1,57 @@
+// Device state and launch entry points of the bddmp kernels (kernels.hip). The host orchestration
+// in solver.hip only calls these functions; each returns the launch's hipError_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace bddmp {
+
+constexpr int kFwd = 0, kBwd = 1;
+constexpr int kUpdate = 0;    // min-marginals, J_i sum, multiplier update, then step
+constexpr int kNoUpdate = 1;  // step only (initial backward sweep)
+constexpr int kExtract = 2;   // min-marginals to the outputs, then step with unchanged multipliers
+constexpr int kLbStage = 256; // fixed chunk count of the bound reduction
+
+// Pointers into the caller's arena (see ArenaLayout) and the per-call outputs.
+struct Dev {
+  const uint32_t *meta;
+  const int32_t *child, *parent;
+  float *lam;
+  float *mf;   // forward messages of each layer's own level (own slots)
+  float *mbc;  // backward messages of each layer's child level (child slots)
+  const uint32_t *garcs;
+  const int4 *grec;
+  const int32_t *canon_of, *layer_of, *layer_var, *root_slot;
+  const int32_t *fwd_tiles, *bwd_tiles, *bwd_list, *fwd_big, *bwd_big;
+  const int32_t *bdd_canon_off;
+  const double *cost;
+  const int32_t *var_first, *var_nj;
+  float *d_fresh, *mbuf;
+  int8_t *xbuf;
+  double *part, *lbpart;
+  double *lb_hist, *scal;
+  float *out0, *out1;
+  int32_t n_bwd_tiles;  // bound partials of big backward tiles start here
+};
+
+// One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).
+// narrow_only selects the variant without wide levels, list the backward index-list variant.
+hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, int tile0, const Dev &D,
+                       hipStream_t s);
+// Big tiles (one variable with more than kTile rows each) of one wave.
+hipError_t launch_wave_big(int dir, int mode, bool list, int nb, int big0, const Dev &D, hipStream_t s);
+
+hipError_t launch_fill(float *p, float v, int n, hipStream_t s);
+hipError_t launch_init_lambda(const Dev &D, int I, hipStream_t s);
+hipError_t launch_root_zero(const Dev &D, int m, hipStream_t s);
+hipError_t launch_lambda_out(const Dev &D, float *out, int I, hipStream_t s);
+hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s);
+hipError_t launch_lb(const Dev &D, int nparts, double lb_const, int slot, hipStream_t s);
+hipError_t launch_residual(const Dev &D, int n, hipStream_t s);
+hipError_t launch_round(const Dev &D, int n, int m, hipStream_t s);
+
+}  // namespace bddmp

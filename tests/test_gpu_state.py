@@ -110,6 +110,47 @@ def test_time_kernels_counts_launches():
     assert s.lower_bound()[0] == pytest.approx(tr[-1], rel=1e-4)
 
 
+def test_full_size_graph_matching_workload():
+    """Graph matching 5000 x 5000, 10 candidates per left node, 200k linearised pairs (greedy-colour
+    order, uneven right degrees, non-contiguous backward waves): 5 iterations element-wise against the
+    oracle, then 195 more checked by properties."""
+    import torch
+
+    ilp = I.config(3)
+    print("[cfg3] plan", flush=True)
+    s, plan = _solver(ilp, hist_cap=1024)
+    assert plan.stats.bwd_contiguous == 0
+    s.iterate(5)
+    hist = s.lb_history(6)
+    lam = s.get_lambda().cpu().numpy().astype(np.float64)
+    m0, m1 = s.min_marginals()
+    m0 = m0.cpu().numpy().astype(np.float64)
+    m1 = m1.cpu().numpy().astype(np.float64)
+    print("[cfg3] oracle", flush=True)
+    o = Oracle(ilp)
+    lb0 = o.init()
+    tr = o.iterate(5)
+    lam_ref = o.lam()
+    r0, r1 = o.min_marginals()
+    assert_trace_close(hist, np.concatenate([[lb0], tr]))
+    scale = incidence_scale(ilp, lam_ref)
+    assert_incidence_close(lam, lam_ref, scale, what="lambda")
+    assert_incidence_close(m0, r0, scale, what="m0")
+    assert_incidence_close(m1, r1, scale, what="m1")
+    del o
+    print("[cfg3] 195 more iterations", flush=True)
+    s.iterate(195)
+    lb, resid, any_lb = s.lower_bound()
+    hist = s.lb_history(1024)
+    lam_end = s.get_lambda().cpu().numpy()
+    torch.cuda.synchronize()
+    assert hist.shape[0] == 201 and np.all(np.isfinite(hist))
+    assert np.all(np.diff(hist) >= -1e-6 * np.abs(hist[1:])), np.diff(hist).min()
+    big = max(1.0, float(np.abs(lam_end).max()), float(np.abs(ilp.cost).max()))
+    assert resid <= 6 * 200 * plan.stats.max_rows_per_var * 2.0 ** -24 * big, resid
+    assert any_lb <= lb + 1e-9
+
+
 def test_full_size_mrf_workload():
     """Potts 256x256, 8 labels (the benchmark workload) at the benchmark's launch configuration:
     the first bounds and sampled multipliers against the oracle, then the whole 500-iteration run

@@ -83,6 +83,7 @@ typedef struct {
   int32_t max_rows_per_var;     /* max |J_i|                                               */
   int32_t bwd_contiguous;       /* 1 if every backward wave is a contiguous layer range    */
   int64_t fwd_tiles, bwd_tiles; /* workgroups per forward / backward pass                  */
+  int32_t n_instances;          /* independent instances in the plan (1 unless batched)   */
 } bddmp_stats;
 
 typedef struct {
@@ -135,6 +136,27 @@ int32_t bddmp_problem_set_order(bddmp_problem *p, const int32_t *perm);
  */
 int32_t bddmp_plan_create(const bddmp_problem *p, const bddmp_options *opt, bddmp_plan **out);
 
+/*
+ * Batched host build: n_inst independent problems solved as one. The plan is that of their
+ * block-diagonal union (variables, rows and orders concatenated in instance order), so one wave
+ * schedule holds every instance: its depth is the largest instance depth, not the sum. The
+ * decomposition (problem (D), Sec. 3.1) splits along instances, so each instance's multipliers,
+ * min-marginals and rounded primal are computed with exactly the operations of its own plan
+ * (bitwise equal results), and its bound is the sum of its rows' terms. Per-incidence and
+ * per-variable outputs are the concatenation of the instances' canonical arrays
+ * (bddmp_plan_instances gives the offsets). probs: host array of n_inst >= 1 problem handles,
+ * copied. Errors as bddmp_plan_create.
+ */
+int32_t bddmp_plan_create_batch(const bddmp_problem *const *probs, int32_t n_inst, const bddmp_options *opt,
+                                bddmp_plan **out);
+
+/*
+ * Offsets of each instance's variables, rows and canonical incidences in the plan's outputs:
+ * host arrays of n_instances + 1 (any may be NULL). A plan from bddmp_plan_create has one
+ * instance.
+ */
+int32_t bddmp_plan_instances(const bddmp_plan *plan, int64_t *var_off, int64_t *row_off, int64_t *inc_off);
+
 /* Sizes of the plan (host). */
 int32_t bddmp_plan_stats(const bddmp_plan *plan, bddmp_stats *out);
 
@@ -181,6 +203,15 @@ int32_t bddmp_solver_iterate(bddmp_solver *s, int32_t n_iters);
  * Any output pointer may be NULL. NONFINITE if the bound is NaN.
  */
 int32_t bddmp_solver_lower_bound(bddmp_solver *s, double *lb, double *residual, double *any_lambda_bound);
+
+/*
+ * Bound of each instance after the last backward sweep, in fp64: the sum over the instance's rows
+ * of E^j (problem (D)) plus the sum of min(0, c_i) over its variables in no row. E^j is recomputed
+ * from the root level's messages with the sweep's own operations, and each instance's rows are
+ * summed in one fixed shape, so a batched plan gives bitwise the values of each instance's own
+ * plan. lb_host: host [n], n must equal n_instances. Synchronises.
+ */
+int32_t bddmp_solver_instance_bounds(bddmp_solver *s, double *lb_host, int32_t n);
 
 /* Copies the last min(cap, recorded) bounds (oldest first) to lb_host; *n_out = count. Synchronises. */
 int32_t bddmp_solver_lb_history(bddmp_solver *s, double *lb_host, int32_t cap, int32_t *n_out);

@@ -40,7 +40,7 @@ class Stats(C.Structure):
                 ("n_arcs_bot", C.c_int64), ("n_incidences", C.c_int64), ("waves_fwd", C.c_int32),
                 ("waves_bwd", C.c_int32), ("device_bytes", C.c_int64), ("max_width", C.c_int32),
                 ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
-                ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64)]
+                ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,6 +65,8 @@ SIGNATURES = {
     "bddmp_problem_add_rows": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
     "bddmp_problem_set_order": (_I32, [_P, _P]),
     "bddmp_plan_create": (_I32, [_P, C.POINTER(Options), C.POINTER(_P)]),
+    "bddmp_plan_create_batch": (_I32, [_P, _I32, C.POINTER(Options), C.POINTER(_P)]),
+    "bddmp_plan_instances": (_I32, [_P, _P, _P, _P]),
     "bddmp_plan_stats": (_I32, [_P, C.POINTER(Stats)]),
     "bddmp_plan_export_order": (_I32, [_P, _P]),
     "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
@@ -73,6 +75,7 @@ SIGNATURES = {
     "bddmp_solver_reset": (_I32, [_P]),
     "bddmp_solver_iterate": (_I32, [_P, _I32]),
     "bddmp_solver_lower_bound": (_I32, [_P, C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
+    "bddmp_solver_instance_bounds": (_I32, [_P, _P, _I32]),
     "bddmp_solver_lb_history": (_I32, [_P, _P, _I32, C.POINTER(_I32)]),
     "bddmp_solver_min_marginals": (_I32, [_P, _P, _P]),
     "bddmp_solver_get_lambda": (_I32, [_P, _P]),
@@ -91,6 +94,11 @@ def lib():
     """Load libbddmp.so (built in-tree by ``paper_2009_00481_amd/build.py``); raise if missing."""
     global _lib
     if _lib is None:
+        # torch first: its HIP runtime carries the soname the library links against, so the
+        # library binds to that same runtime (one runtime, one device context, shared streams).
+        # Loaded the other way round, the process would hold two HIP runtimes.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_2009_00481_amd/build.py "
                               "(the HIP library has no fallback)")
@@ -164,6 +172,22 @@ def bddmp_plan_create(problem, options: Options | None = None):
     return h
 
 
+def bddmp_plan_create_batch(problems, options: Options | None = None):
+    arr = (C.c_void_p * len(problems))(*[p.value if isinstance(p, C.c_void_p) else p for p in problems])
+    h = C.c_void_p()
+    _check(lib().bddmp_plan_create_batch(C.cast(arr, C.c_void_p), len(problems),
+                                         C.byref(options) if options is not None else None, C.byref(h)))
+    return h
+
+
+def bddmp_plan_instances(plan, n_inst: int):
+    v = np.zeros(n_inst + 1, np.int64)
+    r = np.zeros(n_inst + 1, np.int64)
+    c = np.zeros(n_inst + 1, np.int64)
+    _check(lib().bddmp_plan_instances(plan, _ptr(v), _ptr(r), _ptr(c)))
+    return v, r, c
+
+
 def bddmp_plan_stats(plan) -> Stats:
     s = Stats()
     _check(lib().bddmp_plan_stats(plan, C.byref(s)))
@@ -210,6 +234,12 @@ def bddmp_solver_lower_bound(h):
     lb, r, b = C.c_double(), C.c_double(), C.c_double()
     _check(lib().bddmp_solver_lower_bound(h, C.byref(lb), C.byref(r), C.byref(b)))
     return lb.value, r.value, b.value
+
+
+def bddmp_solver_instance_bounds(h, n_inst: int):
+    out = np.zeros(n_inst, np.float64)
+    _check(lib().bddmp_solver_instance_bounds(h, _ptr(out), int(n_inst)))
+    return out
 
 
 def bddmp_solver_lb_history(h, cap: int):
@@ -287,14 +317,24 @@ class Problem:
 
 
 class Plan:
-    def __init__(self, problem: Problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096):
+    """A plan for one problem, or for several independent ones (``problem`` a list: batched)."""
+
+    def __init__(self, problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096):
         o = bddmp_options_default()
         o.order_mode = order_mode
         o.node_budget = node_budget
         o.hist_cap = hist_cap
-        self.n = problem.n
-        self.h = bddmp_plan_create(problem.h, o)
+        if isinstance(problem, (list, tuple)):
+            self.n = sum(p.n for p in problem)
+            self.h = bddmp_plan_create_batch([p.h for p in problem], o)
+        else:
+            self.n = problem.n
+            self.h = bddmp_plan_create(problem.h, o)
         self.stats = bddmp_plan_stats(self.h)
+
+    def instances(self):
+        """(var_off, row_off, inc_off), each [n_instances + 1]."""
+        return bddmp_plan_instances(self.h, int(self.stats.n_instances))
 
     def order(self):
         return bddmp_plan_export_order(self.h, self.n)
@@ -340,6 +380,9 @@ class Solver:
 
     def lb_history(self, cap: int = 1 << 16):
         return bddmp_solver_lb_history(self.h, cap)
+
+    def instance_bounds(self):
+        return bddmp_solver_instance_bounds(self.h, int(self.plan.stats.n_instances))
 
     def min_marginals(self):
         I = self.n_incidences

@@ -136,6 +136,61 @@ int32_t bddmp_plan_create(const bddmp_problem *h, const bddmp_options *opt, bddm
   });
 }
 
+int32_t bddmp_plan_create_batch(const bddmp_problem *const *probs, int32_t n_inst, const bddmp_options *opt,
+                                bddmp_plan **out) {
+  return guarded([&] {
+    if (!out) return set_error(BDDMP_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (n_inst < 1 || !probs) return set_error(BDDMP_INVALID_ARG, "need at least one instance");
+    bddmp::Problem cat;
+    cat.inst_var.push_back(0);
+    cat.inst_row.push_back(0);
+    int64_t nv = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+      if (!probs[k]) return set_error(BDDMP_INVALID_ARG, "null instance " + std::to_string(k));
+      const bddmp::Problem &q = probs[k]->p;
+      if (nv + q.n > INT32_MAX) return set_error(BDDMP_INVALID_ARG, "more than 2^31 - 1 variables in the batch");
+      const int32_t v0 = int32_t(nv);
+      cat.cost.insert(cat.cost.end(), q.cost.begin(), q.cost.end());
+      const int64_t e0 = cat.row_ptr.back();
+      for (size_t r = 1; r < q.row_ptr.size(); ++r) cat.row_ptr.push_back(e0 + q.row_ptr[r]);
+      for (int32_t c : q.col) cat.col.push_back(v0 + c);
+      cat.coef.insert(cat.coef.end(), q.coef.begin(), q.coef.end());
+      cat.sense.insert(cat.sense.end(), q.sense.begin(), q.sense.end());
+      cat.rhs.insert(cat.rhs.end(), q.rhs.begin(), q.rhs.end());
+      if (q.order.empty())
+        for (int32_t i = 0; i < q.n; ++i) cat.order.push_back(v0 + i);
+      else
+        for (int32_t i : q.order) cat.order.push_back(v0 + i);
+      nv += q.n;
+      cat.inst_var.push_back(nv);
+      cat.inst_row.push_back(int64_t(cat.row_ptr.size()) - 1);
+    }
+    cat.n = int32_t(nv);
+    bddmp_options o;
+    if (opt) o = *opt;
+    else bddmp_options_default(&o);
+    auto *pl = new bddmp_plan();
+    const int32_t rc = bddmp::make_plan(cat, o, pl->plan);
+    if (rc != BDDMP_OK) {
+      delete pl;
+      return rc;
+    }
+    *out = pl;
+    return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_plan_instances(const bddmp_plan *h, int64_t *var_off, int64_t *row_off, int64_t *inc_off) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  const bddmp::Plan &P = h->plan;
+  const size_t k = P.inst_var.size();
+  if (var_off) std::memcpy(var_off, P.inst_var.data(), 8 * k);
+  if (row_off) std::memcpy(row_off, P.inst_row.data(), 8 * k);
+  if (inc_off) std::memcpy(inc_off, P.inst_inc.data(), 8 * k);
+  return BDDMP_OK;
+}
+
 int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   if (!h || !out) return set_error(BDDMP_INVALID_ARG, "null plan or out");
   const bddmp::Plan &P = h->plan;
@@ -155,6 +210,7 @@ int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   out->bwd_contiguous = P.bwd_contiguous ? 1 : 0;
   out->fwd_tiles = int64_t(P.fwd_tiles.size() / 2 + P.fwd_big.size() / 2);
   out->bwd_tiles = int64_t(P.bwd_tiles.size() / 2 + P.bwd_big.size() / 2);
+  out->n_instances = int32_t(P.inst_var.size() - 1);
   return BDDMP_OK;
 }
 
@@ -222,6 +278,11 @@ int32_t bddmp_solver_iterate(bddmp_solver *h, int32_t n_iters) {
 int32_t bddmp_solver_lower_bound(bddmp_solver *h, double *lb, double *residual, double *any_lambda_bound) {
   SOLVER_OR_FAIL(h);
   return guarded([&] { return bddmp::solver_lower_bound(*h->s, lb, residual, any_lambda_bound); });
+}
+
+int32_t bddmp_solver_instance_bounds(bddmp_solver *h, double *lb_host, int32_t n) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_instance_bounds(*h->s, lb_host, n); });
 }
 
 int32_t bddmp_solver_lb_history(bddmp_solver *h, double *lb_host, int32_t cap, int32_t *n_out) {

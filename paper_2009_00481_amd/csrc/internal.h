@@ -54,6 +54,9 @@ struct Problem {
   std::vector<int8_t> sense;
   std::vector<int64_t> rhs;
   std::vector<int32_t> order;  // empty = identity
+  // independent instances concatenated into this problem (empty = one instance): offsets of each
+  // instance's variables and rows, [n_inst + 1]
+  std::vector<int64_t> inst_var, inst_row;
 };
 
 // Byte offsets of the solver's arrays inside the device arena.
@@ -62,6 +65,7 @@ struct ArenaLayout {
   size_t fwd_tiles, bwd_tiles, bwd_list, fwd_big, bwd_big;
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
+  size_t inst_row, inst_lb;
   size_t total;
 };
 
@@ -111,6 +115,11 @@ struct Plan {
   std::vector<int64_t> own_slot, cslot; // [I] own-level slot and child-level slot
   int32_t hist_cap = 4096;
   int64_t n_lbpart = 0;               // backward tiles (normal + big) = bound partials per sweep
+  // instances: offsets of variables, rows and canonical incidences [n_inst + 1], and each
+  // instance's constant bound term (sum of min(0, c_i) over its variables in no row)
+  std::vector<int64_t> inst_var, inst_row, inst_inc;
+  std::vector<double> inst_lb_const;
+  std::vector<int32_t> inst_row32;    // inst_row as int32 for the device
   ArenaLayout lay{};
 };
 

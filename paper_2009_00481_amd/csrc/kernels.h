@@ -36,6 +36,8 @@ struct Dev {
   double *lb_hist, *scal;
   float *out0, *out1;
   int32_t n_bwd_tiles;  // bound partials of big backward tiles start here
+  const int32_t *inst_row;  // [n_inst + 1] first row of each instance
+  double *inst_lb;          // [n_inst] per-instance bounds
 };
 
 // One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).
@@ -51,6 +53,9 @@ hipError_t launch_root_zero(const Dev &D, int m, hipStream_t s);
 hipError_t launch_lambda_out(const Dev &D, float *out, int I, hipStream_t s);
 hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s);
 hipError_t launch_lb(const Dev &D, int nparts, double lb_const, int slot, hipStream_t s);
+// Per-instance bound of the last backward sweep (sum over the instance's rows of E^j, recomputed
+// from the messages and multipliers; instance k's constant term is added by the host).
+hipError_t launch_instance_bounds(const Dev &D, int n_inst, hipStream_t s);
 hipError_t launch_residual(const Dev &D, int n, hipStream_t s);
 hipError_t launch_round(const Dev &D, int n, int m, hipStream_t s);
 

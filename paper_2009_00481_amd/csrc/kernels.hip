@@ -338,6 +338,35 @@ __global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, double 
 }
 
 // per variable: g_i = c_i - sum_j lambda^j_i; partial max |g| and sum of min(0, g)
+// E^j of each row from the state a backward sweep leaves: the root level's backward message
+// (Alg. "Backward BDD update step" at the root, the same operations as in the sweep, so the value
+// is bitwise the one the sweep produced). One workgroup per instance sums its rows in a fixed shape.
+__global__ __launch_bounds__(256) void instance_bound_kernel(const Dev D) {
+  __shared__ double sh[4];
+  const int k = int(blockIdx.x);
+  const int j0 = D.inst_row[k], j1 = D.inst_row[k + 1];
+  double acc = 0.0;
+  for (int j = j0 + int(threadIdx.x); j < j1; j += 256) {
+    const int c0 = D.bdd_canon_off[j];
+    if (c0 == D.bdd_canon_off[j + 1]) continue;
+    const int L = D.layer_of[c0];
+    const uint32_t meta = D.meta[L];
+    const float lam = D.lam[L];
+    float e;
+    if (((meta >> kMetaWidthShift) & 3u) != 0u) {
+      const float2 b = reinterpret_cast<const float2 *>(D.mbc)[L];
+      e = fminf(c2val(meta & 3u, b), c2val((meta >> 2) & 3u, b) + lam);
+    } else {
+      const int4 g = D.grec[L];
+      const uint32_t a = D.garcs[g.x];
+      e = fminf(c16val(D.mbc, g.z, a & 0xFFFFu), c16val(D.mbc, g.z, a >> 16) + lam);
+    }
+    acc += double(e);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) D.inst_lb[k] = t;
+}
+
 __global__ __launch_bounds__(256) void residual_partial_kernel(const Dev D, int n) {
   __shared__ double sh[4];
   __shared__ double smax[256];
@@ -528,6 +557,12 @@ hipError_t launch_lb(const Dev &D, int nparts, double lb_const, int slot, hipStr
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, s, D, lb_const, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_instance_bounds(const Dev &D, int n_inst, hipStream_t s) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(instance_bound_kernel, dim3(n_inst), dim3(256), 0, s, D);
   return hipGetLastError();
 }
 

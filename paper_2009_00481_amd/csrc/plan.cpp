@@ -191,6 +191,12 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     if (P.root_slot[j] >= S || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
   for (int32_t i = 0; i < P.n; ++i)
     if (P.var_nj[i] && (P.var_first[i] < 0 || P.var_first[i] + P.var_nj[i] > I)) return "var_first";
+  // instance row ranges: from 0 to m, non-decreasing (the bound kernel reads rows inside them)
+  const size_t ni = P.inst_row32.size();
+  if (ni < 2 || P.inst_row32[0] != 0 || P.inst_row32[ni - 1] != P.m || P.inst_lb_const.size() != ni - 1)
+    return "instances";
+  for (size_t k = 0; k + 1 < ni; ++k)
+    if (P.inst_row32[k + 1] < P.inst_row32[k]) return "instances";
   return "";
 }
 
@@ -544,6 +550,26 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   for (int32_t i = 0; i < n; ++i)
     if (!P.var_nj[i] && p.cost[i] < 0) P.lb_const += p.cost[i];
 
+  // instances (one unless the problem concatenates several)
+  if (p.inst_var.empty()) {
+    P.inst_var = {0, n};
+    P.inst_row = {0, m};
+  } else {
+    P.inst_var = p.inst_var;
+    P.inst_row = p.inst_row;
+  }
+  const size_t n_inst = P.inst_var.size() - 1;
+  P.inst_inc.assign(n_inst + 1, 0);
+  P.inst_lb_const.assign(n_inst, 0.0);
+  P.inst_row32.assign(n_inst + 1, 0);
+  for (size_t k = 0; k <= n_inst; ++k) {
+    P.inst_inc[k] = P.canon_off[size_t(P.inst_row[k])];
+    P.inst_row32[k] = int32_t(P.inst_row[k]);
+  }
+  for (size_t k = 0; k < n_inst; ++k)
+    for (int64_t i = P.inst_var[k]; i < P.inst_var[k + 1]; ++i)
+      if (!P.var_nj[size_t(i)] && p.cost[size_t(i)] < 0) P.inst_lb_const[k] += p.cost[size_t(i)];
+
   // arena layout
   ArenaLayout &A = P.lay;
   size_t off = 0;
@@ -581,6 +607,8 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.lbpart = take(8 * size_t(P.n_lbpart + 1));
   A.lb_hist = take(8 * size_t(P.hist_cap));
   A.scal = take(256);
+  A.inst_row = take(4 * P.inst_row32.size());
+  A.inst_lb = take(8 * P.inst_lb_const.size());
   A.total = off;
   const std::string bad = validate_layout(P, ownw, childw, level);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);

@@ -15,6 +15,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
 int32_t solver_reset(Solver &S);
 int32_t solver_iterate(Solver &S, int32_t n);
 int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_lambda_bound);
+int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n);
 int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out);
 int32_t solver_min_marginals(Solver &S, float *m0, float *m1);
 int32_t solver_get_lambda(Solver &S, float *lam);

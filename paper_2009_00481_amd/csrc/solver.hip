@@ -160,6 +160,8 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.scal = reinterpret_cast<double *>(b + A.scal);
   D.out0 = D.out1 = nullptr;
   D.n_bwd_tiles = int32_t(P.bwd_tiles.size() / 2);
+  D.inst_row = reinterpret_cast<const int32_t *>(b + A.inst_row);
+  D.inst_lb = reinterpret_cast<double *>(b + A.inst_lb);
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
     if (!nbytes) return hipSuccess;
@@ -184,6 +186,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.cost, P.cost.data(), 8 * P.cost.size()),
       up(A.var_first, P.var_first.data(), 4 * P.var_first.size()),
       up(A.var_nj, P.var_nj.data(), 4 * P.var_nj.size()),
+      up(A.inst_row, P.inst_row32.data(), 4 * P.inst_row32.size()),
   };
   for (hipError_t e : errs)
     if (e != hipSuccess) {
@@ -236,6 +239,18 @@ int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_
   if (residual) *residual = sc[0];
   if (any_lambda_bound) *any_lambda_bound = h + sc[1];
   if (std::isnan(h)) return set_error(BDDMP_NONFINITE, "lower bound is NaN");
+  return BDDMP_OK;
+}
+
+int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n) {
+  const Plan &P = *S.plan;
+  const int32_t n_inst = int32_t(P.inst_lb_const.size());
+  if (!lb_host || n != n_inst)
+    return set_error(BDDMP_INVALID_ARG, "lb array must hold n_instances = " + std::to_string(n_inst) + " values");
+  if (int32_t rc = launched(launch_instance_bounds(S.D, n_inst, S.stream), "instance_bounds")) return rc;
+  HIP_TRY(hipMemcpyAsync(lb_host, S.D.inst_lb, 8 * size_t(n_inst), hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
+  for (int32_t k = 0; k < n_inst; ++k) lb_host[k] += P.inst_lb_const[size_t(k)];
   return BDDMP_OK;
 }
 

@@ -17,6 +17,14 @@ Workload recipes (ILP formulations of App. E):
   pairwise simplex row is implied and omitted).
 - ``graph_matching``: assignment variables with <=1 rows on both sides and
   linearised pair products (App. E.2 with a sparse, linearised pair term).
+- ``tomography``: discrete tomography (App. E.3): a 3-label Potts grid with
+  zero unary costs plus one projection row per image row, column and diagonal
+  (both directions) whose right-hand side comes from a random ground truth.
+- ``tracking``: flow-conservation rows over detections in consecutive frames
+  (the structure of the cell-tracking instances, App. E.4, without the
+  division and exclusion rows).
+- ``batch_config``: the uneven mix of tomography and tracking instances that
+  the batched solver takes in one schedule.
 - ``random_ilp``: small mixed-sense rows with coefficients in [-3, 3].
 """
 from __future__ import annotations
@@ -115,6 +123,8 @@ def potts_grid(H: int, W: int, L: int, *, unary: str = "normal", weight=(0.2, 1.
         un = rng.random((nV, L), dtype=np.float32)
     elif unary == "normal":
         un = rng.standard_normal((nV, L), dtype=np.float32)
+    elif unary == "zero":
+        un = np.zeros((nV, L), dtype=np.float32)
     else:
         raise ValueError(unary)
     if isinstance(weight, (tuple, list)):
@@ -262,6 +272,10 @@ def greedy_colour_order(ilp: ILP) -> np.ndarray:
     Variables are coloured in index order with the smallest colour unused by
     already coloured neighbours; the order lists colour 0 first, then colour 1,
     and so on, index order within a colour.
+
+    The colours of a variable's coloured neighbours are the union, over its
+    rows, of the colours already taken in that row, so each row keeps the set
+    of its members' colours as a bit set.
     """
     n, m = ilp.n, ilp.m
     rp, col = ilp.row_ptr, ilp.col
@@ -272,21 +286,163 @@ def greedy_colour_order(ilp: ILP) -> np.ndarray:
     vptr = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(col, minlength=n), out=vptr[1:])
     colour = np.full(n, -1, np.int64)
-    rp_l, col_l = rp.tolist(), col.tolist()
     vptr_l, vrows_l = vptr.tolist(), vrows.tolist()
+    taken = [0] * m
     for v in range(n):
-        used = set()
-        for q in range(vptr_l[v], vptr_l[v + 1]):
-            j = vrows_l[q]
-            for t in range(rp_l[j], rp_l[j + 1]):
-                cu = colour[col_l[t]]
-                if cu >= 0:
-                    used.add(int(cu))
-        c = 0
-        while c in used:
-            c += 1
+        rows = vrows_l[vptr_l[v]:vptr_l[v + 1]]
+        used = 0
+        for j in rows:
+            used |= taken[j]
+        c = (~used & (used + 1)).bit_length() - 1
         colour[v] = c
+        bit = 1 << c
+        for j in rows:
+            taken[j] |= bit
     return np.argsort(colour, kind="stable").astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Discrete tomography (App. E.3) and tracking-style flow instances (App. E.4)
+# ---------------------------------------------------------------------------
+
+def tomography_truth(P: int, seed: int) -> np.ndarray:
+    """Ground-truth image: label 0 background and ceil(P/8) discs painted in turn, each with a
+    uniform centre in [0, P)^2, radius U[P/16, P/4] and label 1 or 2 (later discs on top)."""
+    rng = np.random.default_rng(seed)
+    img = np.zeros((P, P), np.int64)
+    ii, jj = np.meshgrid(np.arange(P), np.arange(P), indexing="ij")
+    for _ in range((P + 7) // 8):
+        ci, cj = rng.uniform(0, P, size=2)
+        r = rng.uniform(P / 16, P / 4)
+        lab = int(rng.integers(1, 3))
+        img[(ii - ci) ** 2 + (jj - cj) ** 2 <= r * r] = lab
+    return img
+
+
+def tomography_lines(P: int) -> list:
+    """Projection lines as pixel index arrays: rows, columns, diagonals (i - j constant, from
+    -(P-1)), anti-diagonals (i + j constant, from 0)."""
+    idx = np.arange(P * P, dtype=np.int64).reshape(P, P)
+    lines = [idx[i, :] for i in range(P)] + [idx[:, j] for j in range(P)]
+    lines += [np.diagonal(idx, offset=o).copy() for o in range(-(P - 1), P)]
+    flip = idx[:, ::-1]
+    lines += [np.diagonal(flip, offset=o).copy() for o in range(P - 1, -P, -1)]
+    return lines
+
+
+def tomography(P: int, *, seed: int = 0, potts: float = 0.1, unary: str = "zero", name: str = "") -> ILP:
+    """Discrete tomography on a P x P image with labels {0, 1, 2} (label value = intensity).
+
+    The Potts part is ``potts_grid(P, P, 3)`` with weight ``potts`` on every edge (same variables
+    and rows) and unary costs ``unary``: "zero" (the workload) or "normal" (N(0,1), for tests that
+    need every multiplier to move: with zero unary costs the multipliers of the unary variables in
+    projection rows never leave 0). Then one equality row per projection line (rows, columns, both
+    diagonal directions): sum over its pixels p of 1 x[p,1] + 2 x[p,2] = b, with b the line's sum of
+    ``tomography_truth(P, seed)``; label 0 has coefficient 0 and is left out of the row. The
+    ground truth with consistent pairwise variables is feasible. Order: greedy colouring.
+    """
+    base = potts_grid(P, P, 3, unary=unary, weight=potts, seed=seed)
+    img = tomography_truth(P, seed)
+    flat = img.reshape(-1)
+    rows_v, rows_c, rhs = [], [], []
+    for ln in tomography_lines(P):
+        v = np.stack([ln * 3 + 1, ln * 3 + 2], axis=1).reshape(-1)
+        c = np.tile(np.array([1, 2], np.int64), ln.shape[0])
+        rows_v.append(v)
+        rows_c.append(c)
+        rhs.append(int(flat[ln].sum()))
+    rp2, col2, coef2 = _csr(rows_v, rows_c)
+    nnz0 = base.col.shape[0]
+    row_ptr = np.concatenate([base.row_ptr, nnz0 + rp2[1:]])
+    col = np.concatenate([base.col, col2])
+    coef = np.concatenate([base.coef, coef2])
+    sense = np.concatenate([base.sense, np.zeros(len(rows_v), np.int8)])
+    rhs_all = np.concatenate([base.rhs, np.array(rhs, np.int64)])
+    ilp = ILP(base.n, base.cost, row_ptr, col, coef, sense, rhs_all, base.order,
+              name=name or f"tomo{P}_s{seed}",
+              meta=dict(kind="tomography", P=P, seed=seed, n_lines=len(rows_v), truth=img))
+    ilp.order = greedy_colour_order(ilp)
+    return ilp.check()
+
+
+def tomography_truth_point(ilp: ILP) -> np.ndarray:
+    """The 0/1 point of a tomography instance's ground truth (one-hot pixels, consistent pairs)."""
+    P = ilp.meta["P"]
+    img = ilp.meta["truth"].reshape(-1)
+    x = np.zeros(ilp.n, np.int8)
+    x[np.arange(P * P) * 3 + img] = 1
+    E = grid_edges(P, P)
+    nU = P * P * 3
+    x[nU + np.arange(E.shape[0]) * 9 + img[E[:, 0]] * 3 + img[E[:, 1]]] = 1
+    return x
+
+
+def tracking(D: int, *, seed: int = 0, name: str = "") -> ILP:
+    """Flow conservation over D detections split evenly into F = ceil(D/100) frames.
+
+    Each detection of a frame other than the last links to 1 or 2 distinct random detections of the
+    next frame. Variables: appear a_d = 2d and disappear z_d = 2d + 1 for each detection d, then the
+    links in creation order (frame by frame, source by source). One row per detection:
+    a_d + sum(links into d) - z_d - sum(links out of d) = 0. Costs N(0,1) fp32 (drawn after the
+    structure). Order: index order.
+    """
+    rng = np.random.default_rng(seed)
+    F = (D + 99) // 100
+    bounds = [(f * D) // F for f in range(F + 1)]
+    src, dst = [], []
+    for f in range(F - 1):
+        a0, a1, b0, b1 = bounds[f], bounds[f + 1], bounds[f + 1], bounds[f + 2]
+        for d in range(a0, a1):
+            k = min(int(rng.integers(1, 3)), b1 - b0)
+            for t in rng.choice(b1 - b0, size=k, replace=False):
+                src.append(d)
+                dst.append(b0 + int(t))
+    nlink = len(src)
+    n = 2 * D + nlink
+    cost = rng.standard_normal(n, dtype=np.float32).astype(np.float64)
+    ins = [[] for _ in range(D)]
+    outs = [[] for _ in range(D)]
+    for e, (s_, t_) in enumerate(zip(src, dst)):
+        outs[s_].append(2 * D + e)
+        ins[t_].append(2 * D + e)
+    rows_v, rows_c = [], []
+    for d in range(D):
+        v = [2 * d] + ins[d] + [2 * d + 1] + outs[d]
+        c = [1] * (1 + len(ins[d])) + [-1] * (1 + len(outs[d]))
+        rows_v.append(np.array(v, np.int64))
+        rows_c.append(np.array(c, np.int64))
+    row_ptr, col, coef = _csr(rows_v, rows_c)
+    return ILP(n, cost, row_ptr, col, coef, np.zeros(D, np.int8), np.zeros(D, np.int64),
+               np.arange(n, dtype=np.int32), name=name or f"track{D}_s{seed}",
+               meta=dict(kind="tracking", D=D, frames=F, links=nlink, seed=seed)).check()
+
+
+def batch_config(n_inst: int = 256, *, p_range=(32, 128), d_range=(200, 2000)) -> list:
+    """The batched workload: tomography and tracking instances interleaved (even positions
+    tomography, odd ones tracking), instance seed = position. Sizes from the instance's own seed:
+    P ~ U{p_range}, D ~ U{d_range} (inclusive)."""
+    out = []
+    for k in range(n_inst):
+        r = np.random.default_rng([k, 7])
+        if k % 2 == 0:
+            out.append(tomography(int(r.integers(p_range[0], p_range[1] + 1)), seed=k))
+        else:
+            out.append(tracking(int(r.integers(d_range[0], d_range[1] + 1)), seed=k))
+    return out
+
+
+def concat(ilps: list, name: str = "") -> ILP:
+    """Block-diagonal union of instances: variables, rows and orders concatenated in instance
+    order (instance k's variables shifted by the sizes before it)."""
+    voff = np.cumsum([0] + [q.n for q in ilps])
+    noff = np.cumsum([0] + [q.nnz for q in ilps])
+    row_ptr = np.concatenate([np.zeros(1, np.int64)] + [q.row_ptr[1:] + noff[k] for k, q in enumerate(ilps)])
+    col = np.concatenate([q.col.astype(np.int64) + voff[k] for k, q in enumerate(ilps)]).astype(np.int32)
+    order = np.concatenate([q.order.astype(np.int64) + voff[k] for k, q in enumerate(ilps)]).astype(np.int32)
+    return ILP(int(voff[-1]), np.concatenate([q.cost for q in ilps]), row_ptr, col,
+               np.concatenate([q.coef for q in ilps]), np.concatenate([q.sense for q in ilps]),
+               np.concatenate([q.rhs for q in ilps]), order, name=name or f"concat{len(ilps)}",
+               meta=dict(kind="concat", var_off=voff, row_off=np.cumsum([0] + [q.m for q in ilps]))).check()
 
 
 # ---------------------------------------------------------------------------

@@ -70,8 +70,10 @@ typedef struct {
   int64_t node_budget;    /* max total BDD nodes, 0 = unlimited                                */
   double stop_rel_impr;   /* reserved (iteration counts are explicit), 0                        */
   float alpha;            /* reserved for the smoothed variant, 0 = min-plus                    */
-  int32_t reserved;
-  const char *tiling;     /* reserved, may be NULL                                              */
+  int32_t tile_work;      /* a tile closes once its general levels hold this many own plus next-
+                             level nodes (0: 2048; the node-parallel path stages up to 2048 of each) */
+  const char *tiling;     /* general-layer path by width class, "g0,g1,g2,g3" (NULL: default
+                             "0,0,0,0"); see bddmp_solver_set_groups                             */
 } bddmp_options;
 
 typedef struct {
@@ -239,12 +241,46 @@ int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
 int32_t bddmp_solver_round_primal(bddmp_solver *s, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated);
 
 /*
- * Diagnostics: runs n_iters iterations with a HIP event pair around each forward pass, each
- * backward pass and each bound reduction (not around single launches, so the events add no gap
- * between the waves of a pass) and reports the summed times per class, the launches they cover
- * (one per wave) and the algorithmic bytes of those passes (20 bytes per node and 8 per incidence:
- * arcs 8, messages 12, multiplier 8); then the same number of iterations without events for
- * iter_ms. The solver advances by 2*n_iters iterations. Synchronises.
+ * Launch mode of bddmp_solver_iterate. enable = 1 (default): one iteration (every wave launch of
+ * both passes and the bound reduction) is captured once as a HIP graph on a private stream and
+ * replayed on the solver's stream, one graph launch per iteration; the bound's history slot comes
+ * from a device counter, so replays need no changed arguments. enable = 0: every wave is launched
+ * from the host. Both give bitwise the same results.
+ */
+int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
+
+/*
+ * Path of the general layers (a level or its next level with more than 2 nodes). Tiles are classed
+ * by their widest general level (class 0: <= 8 nodes, 1: <= 32, 2: <= 128, 3: wider); lanes[c]
+ * selects the path for class c:
+ *   0: node-parallel over the tile: every lane takes nodes of the tile's general levels, the next
+ *      levels' messages are staged in LDS, and a layer's min-marginals are integer minima in LDS
+ *      (a tile whose general levels exceed the LDS stage falls back to groups of 64);
+ *   2^k (1..64): one group of 2^k lanes per layer (one wavefront or a sub-wave group): min-marginals
+ *      as per-lane minima and a butterfly minimum over the group.
+ * In both, the forward step is a pull over the next level's in-arcs and the backward step takes
+ * one node per lane. Results do not depend on the choice (every minimum is exact), only speed.
+ * set: host int32[4]; INVALID_ARG unless each is 0 or a power of two up to 64. get: host int32[4].
+ */
+int32_t bddmp_solver_set_groups(bddmp_solver *s, const int32_t *lanes);
+int32_t bddmp_solver_get_groups(const bddmp_solver *s, int32_t *lanes);
+
+/*
+ * Autotuner of the general-layer path: for each width class present in the plan, times iters
+ * iterations with the node-parallel path and each group size 1, 2, ..., 64 (the other classes at
+ * their current choice) and keeps the fastest; lanes (host int32[4], may be NULL) receives the choice. The solver advances by the
+ * iterations run (call bddmp_solver_reset to restart). Synchronises.
+ */
+int32_t bddmp_solver_autotune(bddmp_solver *s, int32_t iters, int32_t *lanes);
+
+/*
+ * Diagnostics: runs n_iters iterations launched from the host with a HIP event pair around each
+ * forward pass, each backward pass and each bound reduction (not around single launches, so the
+ * events add no gap between the waves of a pass) and reports the summed times per class, the
+ * launches they cover (one per wave) and the algorithmic bytes of those passes (20 bytes per node
+ * and 8 per incidence: arcs 8, messages 12, multiplier 8); then the same number of iterations as
+ * bddmp_solver_iterate runs them (graph replays by default) for iter_ms. The solver advances by
+ * 2*n_iters iterations. Synchronises.
  */
 int32_t bddmp_solver_time_kernels(bddmp_solver *s, int32_t n_iters, bddmp_kernel_times *out);
 

@@ -31,7 +31,7 @@ class BddmpError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("order_mode", C.c_int32), ("hist_cap", C.c_int32), ("node_budget", C.c_int64),
-                ("stop_rel_impr", C.c_double), ("alpha", C.c_float), ("reserved", C.c_int32),
+                ("stop_rel_impr", C.c_double), ("alpha", C.c_float), ("tile_work", C.c_int32),
                 ("tiling", C.c_char_p)]
 
 
@@ -81,6 +81,10 @@ SIGNATURES = {
     "bddmp_solver_get_lambda": (_I32, [_P, _P]),
     "bddmp_solver_set_lambda": (_I32, [_P, _P]),
     "bddmp_solver_round_primal": (_I32, [_P, _P, _P, C.POINTER(_D), C.POINTER(_I64)]),
+    "bddmp_solver_set_graphs": (_I32, [_P, _I32]),
+    "bddmp_solver_set_groups": (_I32, [_P, _P]),
+    "bddmp_solver_get_groups": (_I32, [_P, _P]),
+    "bddmp_solver_autotune": (_I32, [_P, _I32, _P]),
     "bddmp_solver_time_kernels": (_I32, [_P, _I32, C.POINTER(KernelTimes)]),
     "bddmp_solver_destroy": (None, [_P]),
     "bddmp_plan_destroy": (None, [_P]),
@@ -269,6 +273,28 @@ def bddmp_solver_round_primal(h, M, n: int):
     return x[:n], obj.value, nv.value
 
 
+def bddmp_solver_set_graphs(h, enable: bool):
+    _check(lib().bddmp_solver_set_graphs(h, int(bool(enable))))
+
+
+def bddmp_solver_set_groups(h, lanes):
+    arr = np.ascontiguousarray(lanes, np.int32)
+    assert arr.shape == (4,)
+    _check(lib().bddmp_solver_set_groups(h, _ptr(arr)))
+
+
+def bddmp_solver_get_groups(h):
+    arr = np.zeros(4, np.int32)
+    _check(lib().bddmp_solver_get_groups(h, _ptr(arr)))
+    return arr
+
+
+def bddmp_solver_autotune(h, iters: int):
+    arr = np.zeros(4, np.int32)
+    _check(lib().bddmp_solver_autotune(h, int(iters), _ptr(arr)))
+    return arr
+
+
 def bddmp_solver_time_kernels(h, n_iters: int) -> KernelTimes:
     t = KernelTimes()
     _check(lib().bddmp_solver_time_kernels(h, int(n_iters), C.byref(t)))
@@ -319,11 +345,15 @@ class Problem:
 class Plan:
     """A plan for one problem, or for several independent ones (``problem`` a list: batched)."""
 
-    def __init__(self, problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096):
+    def __init__(self, problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096,
+                 tiling: str | None = None, tile_work: int = 0):
         o = bddmp_options_default()
+        o.tile_work = tile_work
         o.order_mode = order_mode
         o.node_budget = node_budget
         o.hist_cap = hist_cap
+        self._tiling = tiling.encode() if tiling is not None else None
+        o.tiling = self._tiling
         if isinstance(problem, (list, tuple)):
             self.n = sum(p.n for p in problem)
             self.h = bddmp_plan_create_batch([p.h for p in problem], o)
@@ -406,6 +436,18 @@ class Solver:
         M = self.torch.empty(max(n, 1), dtype=self.torch.float32, device=self.device)
         x, obj, nv = bddmp_solver_round_primal(self.h, M, n)
         return M[:n], x, obj, nv
+
+    def set_graphs(self, enable: bool):
+        bddmp_solver_set_graphs(self.h, enable)
+
+    def set_groups(self, lanes):
+        bddmp_solver_set_groups(self.h, lanes)
+
+    def groups(self):
+        return bddmp_solver_get_groups(self.h)
+
+    def autotune(self, iters: int):
+        return bddmp_solver_autotune(self.h, iters)
 
     def time_kernels(self, n_iters: int) -> dict:
         return bddmp_solver_time_kernels(self.h, n_iters).as_dict()

@@ -313,6 +313,26 @@ int32_t bddmp_solver_round_primal(bddmp_solver *h, float *M_dev, int8_t *x_host,
   return guarded([&] { return bddmp::solver_round_primal(*h->s, M_dev, x_host, obj, n_violated); });
 }
 
+int32_t bddmp_solver_set_graphs(bddmp_solver *h, int32_t enable) {
+  SOLVER_OR_FAIL(h);
+  return bddmp::solver_set_graphs(*h->s, enable);
+}
+
+int32_t bddmp_solver_set_groups(bddmp_solver *h, const int32_t *lanes) {
+  SOLVER_OR_FAIL(h);
+  return bddmp::solver_set_groups(*h->s, lanes);
+}
+
+int32_t bddmp_solver_get_groups(const bddmp_solver *h, int32_t *lanes) {
+  SOLVER_OR_FAIL(h);
+  return bddmp::solver_get_groups(*h->s, lanes);
+}
+
+int32_t bddmp_solver_autotune(bddmp_solver *h, int32_t iters, int32_t *lanes) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_autotune(*h->s, iters, lanes); });
+}
+
 int32_t bddmp_solver_time_kernels(bddmp_solver *h, int32_t n_iters, bddmp_kernel_times *out) {
   SOLVER_OR_FAIL(h);
   if (!out || n_iters < 0) return set_error(BDDMP_INVALID_ARG, "bad arguments");

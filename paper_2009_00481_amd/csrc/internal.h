@@ -28,6 +28,27 @@ constexpr uint32_t kMetaField = 0x3FFu;
 
 // Bit 31 of a backward tile's end position: the tile holds a root level (contributes to the bound).
 constexpr uint32_t kTileRootBit = 0x80000000u;
+// Bits 29-30 of a tile's start position: width class of its widest general level (0: <= 8 nodes,
+// 1: <= 32, 2: <= 128, 3: wider), which selects the lanes per general layer. Positions stay
+// below 2^29.
+constexpr uint32_t kTileClsShift = 29, kTilePosMask = (1u << 29) - 1u;
+constexpr int kWidthClasses = 4;
+// A tile closes early once its general layers hold this many nodes (own plus child level), so
+// that tiles with wide levels carry comparable work (default; options.tile_work overrides).
+constexpr int64_t kTileWideWork = 2048;
+// Packed in-arcs of a next-level node with at most two (two in-arc codes, kNoArc16 for none);
+// kManyInArcs marks a node with more, whose in-arcs are read from the offset lists.
+constexpr uint32_t kNoArc16 = 0xFFFFu, kManyInArcs = 0xFFFFFFFFu;
+// Per tile width class, 4 bits: log2 of the lanes per general layer (0..6), or kGselFlat for the
+// node-parallel tile path. Default: the node-parallel path for every class.
+constexpr uint32_t kGselFlat = 7u;
+constexpr uint32_t kDefaultGsel = kGselFlat | (kGselFlat << 4) | (kGselFlat << 8) | (kGselFlat << 12);
+// Lanes value <-> 4-bit code: 0 (node-parallel) <-> kGselFlat, 2^k (k <= 6) <-> k; false if invalid.
+bool gsel_code(int32_t lanes, uint32_t &code);
+// Parses "g0,g1,g2,g3" (each 0 or a power of two up to 64) into a gsel word; false if malformed.
+bool parse_groups(const char *s, uint32_t &gsel);
+// In-arc codes of the pull-form forward step: source node index (15 bits) | arc label << 15.
+constexpr uint32_t kInArcHi = 0x8000u;
 
 // Records bddmp_last_error's message and returns code.
 int32_t set_error(int32_t code, const std::string &msg);
@@ -61,7 +82,7 @@ struct Problem {
 
 // Byte offsets of the solver's arrays inside the device arena.
 struct ArenaLayout {
-  size_t meta, child, parent, lam, mf, mbc, garcs, grec, canon_of, layer_of, layer_var, root_slot;
+  size_t meta, child, parent, lam, mf, mbc, garcs, grec, gnb, rbeg, rin, rarc, canon_of, layer_of, layer_var, root_slot;
   size_t fwd_tiles, bwd_tiles, bwd_list, fwd_big, bwd_big;
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
@@ -98,7 +119,13 @@ struct Plan {
   std::vector<uint32_t> meta;         // [I] meta word of each layer
   std::vector<int32_t> child, parent; // [I] next / previous level of the same row, -1 at the ends
   std::vector<uint32_t> garcs;        // [S] lo | hi << 16 (16-bit codes) at every node slot
-  std::vector<int32_t> grec;          // [4I] or empty: own slot, own width, child slot, child width
+  // [4I] or empty: own slot, child slot, own width | child width << 16, base of the child level's
+  // in-arc offsets in rbeg (-1 without child level)
+  std::vector<int32_t> grec;
+  std::vector<int32_t> gnb;           // [2I] with grec: child layer's own slot, parent layer's child slot (-1 at row ends)
+  std::vector<int32_t> rbeg;          // per general layer with a child: child width + 1 offsets into rarc
+  std::vector<uint32_t> rin;          // same indexing as rbeg: up to two in-arcs packed, or kManyInArcs
+  std::vector<uint16_t> rarc;         // in-arcs of those child levels (kInArcHi marks 1-arcs)
   std::vector<int32_t> canon_of;      // [I] storage layer -> canonical incidence
   std::vector<int32_t> layer_of;      // [I] canonical incidence -> storage layer
   std::vector<int32_t> layer_var;     // [I] variable of a storage layer
@@ -120,6 +147,11 @@ struct Plan {
   std::vector<int64_t> inst_var, inst_row, inst_inc;
   std::vector<double> inst_lb_const;
   std::vector<int32_t> inst_row32;    // inst_row as int32 for the device
+  // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
+  // of each class over both passes
+  uint32_t gsel = kDefaultGsel;
+  int64_t tile_work = kTileWideWork;
+  int64_t class_tiles[kWidthClasses] = {0, 0, 0, 0};
   ArenaLayout lay{};
 };
 

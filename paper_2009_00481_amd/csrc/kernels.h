@@ -15,6 +15,7 @@ constexpr int kUpdate = 0;    // min-marginals, J_i sum, multiplier update, then
 constexpr int kNoUpdate = 1;  // step only (initial backward sweep)
 constexpr int kExtract = 2;   // min-marginals to the outputs, then step with unchanged multipliers
 constexpr int kLbStage = 256; // fixed chunk count of the bound reduction
+constexpr uint32_t kFlat = 7; // gsel code of the node-parallel path for general layers
 
 // Pointers into the caller's arena (see ArenaLayout) and the per-call outputs.
 struct Dev {
@@ -25,6 +26,10 @@ struct Dev {
   float *mbc;  // backward messages of each layer's child level (child slots)
   const uint32_t *garcs;
   const int4 *grec;
+  const int2 *gnb;        // child layer's own slot, parent layer's child slot (-1 at row ends)
+  const int32_t *rbeg;    // in-arc offsets of general layers' child levels
+  const uint32_t *rin;    // the same nodes' in-arcs packed when at most two (kManyInArcs otherwise)
+  const uint16_t *rarc;   // in-arcs (source node | kInArcHi for a 1-arc)
   const int32_t *canon_of, *layer_of, *layer_var, *root_slot;
   const int32_t *fwd_tiles, *bwd_tiles, *bwd_list, *fwd_big, *bwd_big;
   const int32_t *bdd_canon_off;
@@ -38,6 +43,10 @@ struct Dev {
   int32_t n_bwd_tiles;  // bound partials of big backward tiles start here
   const int32_t *inst_row;  // [n_inst + 1] first row of each instance
   double *inst_lb;          // [n_inst] per-instance bounds
+  long long *hist_n;        // bounds recorded so far (device counter; slot = count % hist_cap)
+  int32_t hist_cap;
+  uint32_t gsel;            // per tile width class, 4 bits: log2 of the lanes per general layer
+                            // (0..6), or kFlat for the node-parallel tile path
 };
 
 // One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).
@@ -52,7 +61,10 @@ hipError_t launch_init_lambda(const Dev &D, int I, hipStream_t s);
 hipError_t launch_root_zero(const Dev &D, int m, hipStream_t s);
 hipError_t launch_lambda_out(const Dev &D, float *out, int I, hipStream_t s);
 hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s);
-hipError_t launch_lb(const Dev &D, int nparts, double lb_const, int slot, hipStream_t s);
+// Bound of the backward sweep just run into the history ring at the device counter's slot, then
+// the counter advances (no host-side argument changes between iterations, so graphs can replay it).
+hipError_t launch_lb(const Dev &D, int nparts, double lb_const, hipStream_t s);
+hipError_t launch_set_counter(const Dev &D, long long value, hipStream_t s);
 // Per-instance bound of the last backward sweep (sum over the instance's rows of E^j, recomputed
 // from the messages and multipliers; instance k's constant term is added by the host).
 hipError_t launch_instance_bounds(const Dev &D, int n_inst, hipStream_t s);

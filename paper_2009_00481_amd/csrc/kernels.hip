@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -41,6 +42,16 @@ __device__ __forceinline__ float updated(float lam0, float d, float share, int n
   return nf == 0 ? (lam0 - d) + share : (isinf(d) ? lam0 + share : lam0 - d);
 }
 
+// General record of a layer: own slot, child slot, own width, child width, base of the child
+// level's in-arc offsets (-1 without child level).
+struct GRec {
+  int os, cs, w, wc, rb;
+};
+__device__ __forceinline__ GRec grec_of(const Dev &D, int L) {
+  const int4 g = D.grec[L];
+  return {g.x, g.y, g.z & 0xFFFF, int(uint32_t(g.z) >> 16), g.w};
+}
+
 // One layer's work split around the J_i sum: begin() computes the min-marginals, push() /
 // bstep() apply the new multiplier in the forward push or the backward step.
 //
@@ -51,14 +62,15 @@ __device__ __forceinline__ float updated(float lam0, float d, float share, int n
 // child slots. tgt is that child (forward) or parent (backward) layer, -1 at a row's end.
 // NARROW_ONLY instantiations serve waves without wide levels: no per-lane branch, so the compiler
 // issues all loads at once instead of sinking the message loads behind the meta word.
-template <int DIR, bool NARROW_ONLY>
+// LOOP: a general layer is handled by its own lane, looping over its nodes (big tiles); otherwise
+// general layers are left to the lane groups of the wave kernel.
+template <int DIR, bool NARROW_ONLY, bool LOOP>
 struct Layer {
   int L;
   int tgt;
   uint32_t meta;
   float lam0;
   float2 f, b;     // narrow: own forward messages, child backward messages
-  int4 g;          // general: own slot, own width, child slot, child width
   float m0, m1;
 
   __device__ __forceinline__ bool narrow() const {
@@ -82,13 +94,13 @@ struct Layer {
       const uint32_t lo0 = meta & 3u, hi0 = (meta >> 2) & 3u, lo1 = (meta >> 4) & 3u, hi1 = (meta >> 6) & 3u;
       m0 = fminf(f.x + c2val(lo0, b), f.y + c2val(lo1, b));
       m1 = fminf((f.x + lam0) + c2val(hi0, b), (f.y + lam0) + c2val(hi1, b));
-    } else {
-      g = D.grec[L];
-      for (int u = 0; u < g.y; ++u) {
-        const uint32_t a = D.garcs[g.x + u];
-        const float fu = D.mf[g.x + u];
-        m0 = fminf(m0, fu + c16val(D.mbc, g.z, a & 0xFFFFu));
-        m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, g.z, a >> 16));
+    } else if (LOOP) {
+      const GRec g = grec_of(D, L);
+      for (int u = 0; u < g.w; ++u) {
+        const uint32_t a = D.garcs[g.os + u];
+        const float fu = D.mf[g.os + u];
+        m0 = fminf(m0, fu + c16val(D.mbc, g.cs, a & 0xFFFFu));
+        m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, g.cs, a >> 16));
       }
     }
   }
@@ -106,13 +118,14 @@ struct Layer {
       const float c1 = fminf(fminf(k0 == 1u ? a0 : INFINITY, k1 == 1u ? a1 : INFINITY),
                              fminf(k2 == 1u ? a2 : INFINITY, k3 == 1u ? a3 : INFINITY));
       reinterpret_cast<float2 *>(D.mf)[tgt] = make_float2(c0, c1);
-    } else {
+    } else if (LOOP) {
+      const GRec g = grec_of(D, L);
       const int cs = D.grec[tgt].x;  // the child layer's own slots
-      for (int q = 0; q < g.w; ++q) D.mf[cs + q] = INFINITY;
-      for (int u = 0; u < g.y; ++u) {
-        const uint32_t a = D.garcs[g.x + u];
+      for (int q = 0; q < g.wc; ++q) D.mf[cs + q] = INFINITY;
+      for (int u = 0; u < g.w; ++u) {
+        const uint32_t a = D.garcs[g.os + u];
         const uint32_t lo = a & 0xFFFFu, hi = a >> 16;
-        const float fu = D.mf[g.x + u];
+        const float fu = D.mf[g.os + u];
         if (lo < kTop) D.mf[cs + int(lo)] = fminf(D.mf[cs + int(lo)], fu);
         if (hi < kTop) D.mf[cs + int(hi)] = fminf(D.mf[cs + int(hi)], fu + lam1);
       }
@@ -123,18 +136,18 @@ struct Layer {
   // stored at the parent layer's child slots; returns the root's new backward message (E^j) on a
   // root level, else 0
   __device__ __forceinline__ double bstep(const Dev &D, float lam1) const {
-    float r;
+    float r = 0.0f;
     if (narrow()) {
       const float n0 = fminf(c2val(meta & 3u, b), c2val((meta >> 2) & 3u, b) + lam1);
       const float n1 = fminf(c2val((meta >> 4) & 3u, b), c2val((meta >> 6) & 3u, b) + lam1);
       if (tgt >= 0) reinterpret_cast<float2 *>(D.mbc)[tgt] = make_float2(n0, n1);
       r = n0;
-    } else {
-      r = 0.0f;
-      const int ps = tgt >= 0 ? D.grec[tgt].z : -1;  // the parent layer's child slots
-      for (int u = 0; u < g.y; ++u) {
-        const uint32_t a = D.garcs[g.x + u];
-        const float v = fminf(c16val(D.mbc, g.z, a & 0xFFFFu), c16val(D.mbc, g.z, a >> 16) + lam1);
+    } else if (LOOP) {
+      const GRec g = grec_of(D, L);
+      const int ps = tgt >= 0 ? D.grec[tgt].y : -1;  // the parent layer's child slots
+      for (int u = 0; u < g.w; ++u) {
+        const uint32_t a = D.garcs[g.os + u];
+        const float v = fminf(c16val(D.mbc, g.cs, a & 0xFFFFu), c16val(D.mbc, g.cs, a >> 16) + lam1);
         if (ps >= 0) D.mbc[ps + u] = v;
         if (u == 0) r = v;
       }
@@ -142,6 +155,108 @@ struct Layer {
     return (meta & kMetaRootBit) ? double(r) : 0.0;
   }
 };
+
+// General layers of a tile. Their records are read once by the layer's own lane and kept in LDS
+// by compact index k (the layer's rank among the tile's general layers, in position order).
+struct GenTile {
+  int os[kTile], cs[kTile], ww[kTile], rb[kTile], osc[kTile], pcs[kTile];
+  int wo[kTile + 1], co[kTile + 1];  // exclusive prefix sums of own / child level widths
+  float lam[kTile];
+  unsigned m0[kTile], m1[kTile];     // min-marginals as order-preserving integers
+  float e[kTile];                    // new backward message of node 0 (the root value on a root level)
+};
+
+// float <-> unsigned with the same order (for integer min in LDS; a bijection, so exact)
+__device__ __forceinline__ unsigned ord_of(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float float_of(unsigned u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// Forward step of next-level node v of a general layer (pull form of Alg. "Forward BDD update
+// step"): the minimum over its in-arcs of (source forward message + lam on a 1-arc). fu_of(u)
+// gives the forward message of this level's node u.
+template <class F>
+__device__ __forceinline__ float pull_min(const Dev &D, int rb, int v, float lam, F fu_of) {
+  const uint32_t pk = D.rin[rb + v];
+  if (pk != kManyInArcs) {
+    const uint32_t a0 = pk & 0xFFFFu, a1 = pk >> 16;
+    const float f0 = fu_of(int(a0 & (kInArcHi - 1u)));
+    float val = (a0 & kInArcHi) ? f0 + lam : f0;
+    if (a1 != kNoArc16) {
+      const float f1 = fu_of(int(a1 & (kInArcHi - 1u)));
+      val = fminf(val, (a1 & kInArcHi) ? f1 + lam : f1);
+    }
+    return val;
+  }
+  const int b0 = D.rbeg[rb + v], b1 = D.rbeg[rb + v + 1];
+  float val = INFINITY;
+  for (int q = b0; q < b1; ++q) {
+    const uint32_t a = D.rarc[q];
+    const float fu = fu_of(int(a & (kInArcHi - 1u)));
+    val = fminf(val, (a & kInArcHi) ? fu + lam : fu);
+  }
+  return val;
+}
+
+// Group path: one general layer per group of G lanes (G a power of two up to 64; groups are
+// aligned inside a wavefront, so a group's shuffles stay among its own lanes, which share their
+// control flow). gl is the lane's index in its group.
+
+// min-marginals: each lane minimises over its nodes, then a butterfly min over the group (min is
+// exact, so the result does not depend on how nodes are split among lanes)
+__device__ __forceinline__ float2 group_mm(const Dev &D, const GenTile &T, int k, int gl, int G) {
+  const int os = T.os[k], cs = T.cs[k], w = T.ww[k] & 0xFFFF;
+  const float lam0 = T.lam[k];
+  float m0 = INFINITY, m1 = INFINITY;
+  for (int u = gl; u < w; u += G) {
+    const uint32_t a = D.garcs[os + u];
+    const float fu = D.mf[os + u];
+    m0 = fminf(m0, fu + c16val(D.mbc, cs, a & 0xFFFFu));
+    m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, cs, a >> 16));
+  }
+  for (int o = G >> 1; o > 0; o >>= 1) {
+    m0 = fminf(m0, __shfl_xor(m0, o, 64));
+    m1 = fminf(m1, __shfl_xor(m1, o, 64));
+  }
+  return make_float2(m0, m1);
+}
+
+// forward step of the next level in pull form: each lane takes next-level nodes and minimises
+// over their in-arcs (Alg. "Forward BDD update step"), so no two lanes write one slot
+__device__ __forceinline__ void group_push(const Dev &D, const GenTile &T, int k, int gl, int G) {
+  const int osc = T.osc[k];
+  if (osc < 0) return;
+  const int os = T.os[k], wc = int(unsigned(T.ww[k]) >> 16), rb = T.rb[k];
+  const float lam1 = T.lam[k];
+  for (int v = gl; v < wc; v += G) D.mf[osc + v] = pull_min(D, rb, v, lam1, [&](int u) { return D.mf[os + u]; });
+}
+
+// backward step of this level, one node per lane; returns node 0's new message in lane 0
+__device__ __forceinline__ float group_bstep(const Dev &D, const GenTile &T, int k, int gl, int G) {
+  const int os = T.os[k], cs = T.cs[k], w = T.ww[k] & 0xFFFF, ps = T.pcs[k];
+  const float lam1 = T.lam[k];
+  float r = 0.0f;
+  for (int u = gl; u < w; u += G) {
+    const uint32_t a = D.garcs[os + u];
+    const float v = fminf(c16val(D.mbc, cs, a & 0xFFFFu), c16val(D.mbc, cs, a >> 16) + lam1);
+    if (ps >= 0) D.mbc[ps + u] = v;
+    if (u == 0) r = v;
+  }
+  return r;
+}
+
+// Flat path: the tile's general nodes spread over all lanes (node t of the concatenated own
+// levels, kFlatR per lane), with the child levels' backward messages and the own levels' forward
+// messages staged in LDS. A layer's min-marginals are integer minima in LDS (exact).
+constexpr int kFlatCap = 2048;             // own nodes and child nodes a tile may stage
+constexpr int kFlatR = kFlatCap / kTile;   // nodes per lane
+
+__device__ __forceinline__ float staged(const float *cb, int c0, uint32_t c) {
+  return c < kTop ? cb[c0 + int(c)] : (c == kTop ? 0.0f : INFINITY);
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8, each XCD
 // with its own L2). Remap so that XCD x takes one contiguous run of the launch's tiles: lines at a
@@ -168,15 +283,24 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 }
 
 // LIST: backward positions go through bwd_list (a wave that is not one contiguous layer range).
+// Narrow layers run one per lane. General layers (a level or its child level wider than 2) are
+// collected per tile and run either node-parallel over the whole tile (flat path) or by groups of
+// G lanes, as the tile's width class selects.
 template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
 __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0) {
   __shared__ float s_d[kTile];
   __shared__ float s_share[kTile];
   __shared__ int s_nf[kTile];
-  __shared__ double s_red[kTile / 64];
+  __shared__ int s_wcnt[kTile / 64];
+  // LDS of the general-layer paths (one element in narrow-only instantiations)
+  __shared__ std::conditional_t<NARROW_ONLY, int, GenTile> s_g;
+  __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap], s_fu[NARROW_ONLY ? 1 : kFlatCap];
+  // node -> compact layer index of the flat path (own and next-level nodes)
+  __shared__ uint8_t s_mo[NARROW_ONLY ? 1 : kFlatCap], s_mc[NARROW_ONLY ? 1 : kFlatCap];
   const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
   const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
-  const int p0 = tiles[2 * tix];
+  const uint32_t w0 = uint32_t(tiles[2 * tix]);
+  const int p0 = int(w0 & kTilePosMask);
   // a backward tile's end carries bit 31 when the tile holds a root level
   const uint32_t end = uint32_t(tiles[2 * tix + 1]);
   const bool roots = DIR == kBwd && (end & kTileRootBit) != 0u;
@@ -184,11 +308,190 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   const int s = int(threadIdx.x);
   const bool active = s < cnt;
 
-  Layer<DIR, NARROW_ONLY> ly;
+  Layer<DIR, NARROW_ONLY, false> ly;
   ly.meta = 0;
   ly.lam0 = 0.0f;
   ly.m0 = ly.m1 = 0.0f;
-  if (active) ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
+  ly.tgt = -1;
+  int4 grec = make_int4(0, 0, 0, 0);
+  int2 gnb = make_int2(-1, -1);
+  if (active) {
+    const int L = (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s;
+    if (!NARROW_ONLY) {
+      grec = D.grec[L];
+      gnb = D.gnb[L];
+    }
+    ly.begin(D, L);
+  }
+
+  bool gen = false;
+  int ngen = 0, myk = 0, mode = 0, G = 1, TW = 0, TC = 0;
+  bool flat = false;
+  uint32_t ar[NARROW_ONLY ? 1 : kFlatR];
+  float fr[NARROW_ONLY ? 1 : kFlatR];
+  int kr[NARROW_ONLY ? 1 : kFlatR];
+  if constexpr (!NARROW_ONLY) {
+    GenTile &T = s_g;
+    // compact index of the tile's general layers (ballot prefix per wavefront), and exclusive
+    // prefix sums of their own and child widths (scan over the tile in position order)
+    gen = active && !ly.narrow();
+    const uint64_t mask = __ballot(gen);
+    const int lane = s & 63, wv = s >> 6;
+    const int w = gen ? (grec.z & 0xFFFF) : 0, wc = gen ? int(unsigned(grec.z) >> 16) : 0;
+    int iw = w, ic = wc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tw = __shfl_up(iw, o, 64), tc = __shfl_up(ic, o, 64);
+      if (lane >= o) {
+        iw += tw;
+        ic += tc;
+      }
+    }
+    if (lane == 63) {
+      s_wcnt[wv] = __popcll(mask);
+      s_d[wv] = __int_as_float(iw);
+      s_share[wv] = __int_as_float(ic);
+    }
+    __syncthreads();
+    int koff = 0, woff = 0, coff = 0;
+    for (int q = 0; q < kTile / 64; ++q) {
+      if (q < wv) {
+        koff += s_wcnt[q];
+        woff += __float_as_int(s_d[q]);
+        coff += __float_as_int(s_share[q]);
+      }
+      ngen += s_wcnt[q];
+      TW += __float_as_int(s_d[q]);
+      TC += __float_as_int(s_share[q]);
+    }
+    __syncthreads();
+    if (gen) {
+      myk = koff + __popcll(mask & ((1ull << lane) - 1ull));
+      T.os[myk] = grec.x;
+      T.cs[myk] = grec.y;
+      T.ww[myk] = grec.z;
+      T.rb[myk] = grec.w;
+      T.osc[myk] = gnb.x;
+      T.pcs[myk] = gnb.y;
+      T.wo[myk] = woff + iw - w;
+      T.co[myk] = coff + ic - wc;
+      T.lam[myk] = ly.lam0;
+      T.m0[myk] = T.m1[myk] = ord_of(INFINITY);
+    }
+    mode = int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
+    flat = mode == int(kFlat) && TW <= kFlatCap && TC <= kFlatCap;
+    G = mode == int(kFlat) ? 64 : (1 << mode);
+    if (flat) {
+      // node -> layer maps: each layer marks its first own (next-level) node, then a prefix max
+      // over the nodes (layers are in ascending node order)
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        s_mo[s * kFlatR + r] = 0;
+        s_mc[s * kFlatR + r] = 0;
+      }
+    }
+    __syncthreads();
+    if (flat) {
+      if (gen) {
+        s_mo[T.wo[myk]] = uint8_t(myk);
+        if (wc > 0) s_mc[T.co[myk]] = uint8_t(myk);
+      }
+      __syncthreads();
+      int mo = 0, mc = 0;
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        mo = max(mo, int(s_mo[s * kFlatR + r]));
+        mc = max(mc, int(s_mc[s * kFlatR + r]));
+      }
+      for (int o = 1; o < 64; o <<= 1) {
+        const int to = __shfl_up(mo, o, 64), tc = __shfl_up(mc, o, 64);
+        if (lane >= o) {
+          mo = max(mo, to);
+          mc = max(mc, tc);
+        }
+      }
+      if (lane == 63) s_wcnt[wv] = mo | (mc << 16);
+      __syncthreads();
+      int po = __shfl_up(mo, 1, 64), pc = __shfl_up(mc, 1, 64);
+      if (lane == 0) po = pc = 0;
+      for (int q = 0; q < wv; ++q) {
+        po = max(po, s_wcnt[q] & 0xFFFF);
+        pc = max(pc, s_wcnt[q] >> 16);
+      }
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        po = max(po, int(s_mo[s * kFlatR + r]));
+        pc = max(pc, int(s_mc[s * kFlatR + r]));
+        s_mo[s * kFlatR + r] = uint8_t(po);
+        s_mc[s * kFlatR + r] = uint8_t(pc);
+      }
+      __syncthreads();
+      // own nodes: arcs and forward messages; child nodes: backward messages into LDS
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        const int t = s + r * kTile;
+        kr[r] = -1;
+        if (t < TW) {
+          const int k = s_mo[t];
+          const int u = t - T.wo[k];
+          kr[r] = k;
+          ar[r] = D.garcs[T.os[k] + u];
+          fr[r] = D.mf[T.os[k] + u];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        const int t = s + r * kTile;
+        if (t < TC) {
+          const int k = s_mc[t];
+          s_cb[t] = D.mbc[T.cs[k] + (t - T.co[k])];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        const int k = kr[r];
+        float m0 = INFINITY, m1 = INFINITY;
+        if (k >= 0) {
+          const int c0 = T.co[k];
+          const float lam0 = T.lam[k];
+          m0 = fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu);
+          m1 = (fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16);
+          s_fu[s + r * kTile] = fr[r];
+        }
+        // a wavefront whose 64 nodes all belong to one layer reduces first (one LDS atomic
+        // instead of 64 on the same word); min is exact, so the order does not matter
+        const int k0 = __shfl(k, 0, 64), k63 = __shfl(k, 63, 64);
+        if (k0 == k63 && k0 >= 0) {
+          for (int o = 32; o > 0; o >>= 1) {
+            m0 = fminf(m0, __shfl_xor(m0, o, 64));
+            m1 = fminf(m1, __shfl_xor(m1, o, 64));
+          }
+          if (lane == 0) {
+            atomicMin(&T.m0[k0], ord_of(m0));
+            atomicMin(&T.m1[k0], ord_of(m1));
+          }
+        } else if (k >= 0) {
+          atomicMin(&T.m0[k], ord_of(m0));
+          atomicMin(&T.m1[k], ord_of(m1));
+        }
+      }
+    } else {
+      const int grp = s / G, gl = s % G, ngrp = kTile / G;
+      for (int k = grp; k < ngen; k += ngrp) {
+        const float2 mm = group_mm(D, T, k, gl, G);
+        if (gl == 0) {
+          T.m0[k] = ord_of(mm.x);
+          T.m1[k] = ord_of(mm.y);
+        }
+      }
+    }
+    __syncthreads();
+    if (gen) {
+      ly.m0 = float_of(T.m0[myk]);
+      ly.m1 = float_of(T.m1[myk]);
+    }
+  }
+
   const float d = ly.m1 - ly.m0;
   float lam1 = ly.lam0;
   if (MODE == kUpdate) {
@@ -221,10 +524,58 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     if (D.out1) D.out1[c] = ly.m1;
     D.d_fresh[ly.L] = d;
   }
+  if constexpr (!NARROW_ONLY) {
+    GenTile &T = s_g;
+    if (gen) T.lam[myk] = lam1;
+    __syncthreads();
+    if (flat) {
+      if (DIR == kFwd) {
+        // next-level nodes over all lanes, each the minimum over its in-arcs (pull form of Alg.
+        // "Forward BDD update step"), reading this level's forward messages from LDS
+#pragma unroll
+        for (int r = 0; r < kFlatR; ++r) {
+          const int t = s + r * kTile;
+          if (t < TC) {
+            const int k = s_mc[t];
+            const int osc = T.osc[k];
+            if (osc >= 0) {
+              const int v = t - T.co[k], f0 = T.wo[k];
+              D.mf[osc + v] = pull_min(D, T.rb[k], v, T.lam[k], [&](int u) { return s_fu[f0 + u]; });
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < kFlatR; ++r) {
+          const int k = kr[r];
+          if (k >= 0) {
+            const int u = s + r * kTile - T.wo[k], c0 = T.co[k], ps = T.pcs[k];
+            const float v = fminf(staged(s_cb, c0, ar[r] & 0xFFFFu), staged(s_cb, c0, ar[r] >> 16) + T.lam[k]);
+            if (ps >= 0) D.mbc[ps + u] = v;
+            if (u == 0) T.e[k] = v;
+          }
+        }
+      }
+    } else {
+      const int grp = s / G, gl = s % G, ngrp = kTile / G;
+      for (int k = grp; k < ngen; k += ngrp) {
+        if (DIR == kFwd) {
+          group_push(D, T, k, gl, G);
+        } else {
+          const float r = group_bstep(D, T, k, gl, G);
+          if (gl == 0) T.e[k] = r;
+        }
+      }
+    }
+    if (DIR == kBwd) __syncthreads();
+  }
   if (DIR == kFwd) {
-    if (active) ly.push(D, lam1);
+    if (active && !gen) ly.push(D, lam1);
   } else {
-    const double e = active ? ly.bstep(D, lam1) : 0.0;
+    double e = 0.0;
+    if (active && !gen) e = ly.bstep(D, lam1);
+    if constexpr (!NARROW_ONLY)
+      if (gen && (ly.meta & kMetaRootBit)) e = double(s_g.e[myk]);
     // bound partial per wavefront: a fixed butterfly, only in tiles holding root levels (the
     // branch is uniform over the workgroup)
     double v = 0.0;
@@ -248,7 +599,7 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
   const int p0 = big[2 * b];
   const int cnt = big[2 * b + 1] - p0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    Layer<DIR, false> ly;
+    Layer<DIR, false, true> ly;
     ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
     s_d[s] = ly.m1 - ly.m0;
     if (MODE == kExtract) {
@@ -274,7 +625,7 @@ __global__ __launch_bounds__(kTile) void wave_big_kernel(const Dev D, const int 
   }
   double e = 0.0;
   for (int s = int(threadIdx.x); s < cnt; s += kTile) {
-    Layer<DIR, false> ly;
+    Layer<DIR, false, true> ly;
     ly.begin(D, (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s);
     float lam1 = ly.lam0;
     if (MODE == kUpdate) {
@@ -331,13 +682,20 @@ __global__ __launch_bounds__(256) void lb_stage_kernel(const Dev D, int nparts) 
   if (threadIdx.x == 0) D.part[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, double lb_const, int slot) {
+__global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, double lb_const) {
   __shared__ double sh[kLbStage / 64];
   const double s = block_sum(D.part[threadIdx.x], sh);
-  if (threadIdx.x == 0) D.lb_hist[slot] = s + lb_const;
+  if (threadIdx.x == 0) {
+    const long long n = *D.hist_n;
+    D.lb_hist[n % D.hist_cap] = s + lb_const;
+    *D.hist_n = n + 1;
+  }
 }
 
-// per variable: g_i = c_i - sum_j lambda^j_i; partial max |g| and sum of min(0, g)
+__global__ void set_counter_kernel(const Dev D, long long value) {
+  if (threadIdx.x == 0) *D.hist_n = value;
+}
+
 // E^j of each row from the state a backward sweep leaves: the root level's backward message
 // (Alg. "Backward BDD update step" at the root, the same operations as in the sweep, so the value
 // is bitwise the one the sweep produced). One workgroup per instance sums its rows in a fixed shape.
@@ -359,7 +717,7 @@ __global__ __launch_bounds__(256) void instance_bound_kernel(const Dev D) {
     } else {
       const int4 g = D.grec[L];
       const uint32_t a = D.garcs[g.x];
-      e = fminf(c16val(D.mbc, g.z, a & 0xFFFFu), c16val(D.mbc, g.z, a >> 16) + lam);
+      e = fminf(c16val(D.mbc, g.y, a & 0xFFFFu), c16val(D.mbc, g.y, a >> 16) + lam);
     }
     acc += double(e);
   }
@@ -367,6 +725,7 @@ __global__ __launch_bounds__(256) void instance_bound_kernel(const Dev D) {
   if (threadIdx.x == 0) D.inst_lb[k] = t;
 }
 
+// per variable: g_i = c_i - sum_j lambda^j_i; partial max |g| and sum of min(0, g)
 __global__ __launch_bounds__(256) void residual_partial_kernel(const Dev D, int n) {
   __shared__ double sh[4];
   __shared__ double smax[256];
@@ -552,11 +911,16 @@ hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_lb(const Dev &D, int nparts, double lb_const, int slot, hipStream_t s) {
+hipError_t launch_lb(const Dev &D, int nparts, double lb_const, hipStream_t s) {
   hipLaunchKernelGGL(lb_stage_kernel, dim3(kLbStage), dim3(256), 0, s, D, nparts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, s, D, lb_const, slot);
+  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, s, D, lb_const);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_counter(const Dev &D, long long value, hipStream_t s) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, D, value);
   return hipGetLastError();
 }
 

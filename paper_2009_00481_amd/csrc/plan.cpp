@@ -16,6 +16,7 @@
 // therefore one contiguous segment, and each wave is one contiguous layer range. Node arrays
 // follow the layer order. Arcs are packed as two 16-bit child codes per node.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -59,17 +60,51 @@ void greedy_colour_order(const Problem &p, std::vector<int32_t> &order) {
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return colour[x] < colour[y]; });
 }
 
+bool gsel_code(int32_t lanes, uint32_t &code) {
+  if (lanes == 0) {
+    code = kGselFlat;
+    return true;
+  }
+  if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))) return false;
+  code = 0;
+  while ((1 << code) < lanes) ++code;
+  return true;
+}
+
+bool parse_groups(const char *s, uint32_t &gsel) {
+  uint32_t out = 0;
+  int k = 0;
+  const char *p = s;
+  while (k < kWidthClasses) {
+    char *e = nullptr;
+    const long v = std::strtol(p, &e, 10);
+    uint32_t code = 0;
+    if (e == p || v > 64 || !gsel_code(int32_t(v), code)) return false;
+    out |= code << (4 * k);
+    ++k;
+    p = e;
+    if (k < kWidthClasses) {
+      if (*p != ',') return false;
+      ++p;
+    }
+  }
+  if (*p) return false;
+  gsel = out;
+  return true;
+}
+
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile;
-// a variable with more rows than kTile gets a big tile of its own. Tiles are (start, end) pairs.
-void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj, int64_t pos0,
-               std::vector<int32_t> &tiles, std::vector<int32_t> &big, WaveRange &wr) {
+// Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile and
+// their general levels hold at most cap nodes (wwork: per variable); a variable with
+// more rows than kTile gets a big tile of its own. Tiles are (start, end) pairs.
+void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj, const std::vector<int64_t> &wwork,
+               int64_t cap, int64_t pos0, std::vector<int32_t> &tiles, std::vector<int32_t> &big, WaveRange &wr) {
   wr.tile_begin = int32_t(tiles.size() / 2);
   wr.big_begin = int32_t(big.size() / 2);
-  int64_t pos = pos0, start = pos0;
+  int64_t pos = pos0, start = pos0, work = 0;
   int32_t cnt = 0;
   for (int32_t i : vars) {
     const int32_t c = nj[i];
@@ -80,16 +115,19 @@ void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj,
       pos += c;
       start = pos;
       cnt = 0;
+      work = 0;
       continue;
     }
-    if (cnt + c > kTile) {
+    if (cnt + c > kTile || (cnt && work + wwork[i] > cap)) {
       tiles.push_back(int32_t(start));
       tiles.push_back(int32_t(pos));
       start = pos;
       cnt = 0;
+      work = 0;
     }
     pos += c;
     cnt += c;
+    work += wwork[i];
   }
   if (cnt) { tiles.push_back(int32_t(start)); tiles.push_back(int32_t(pos)); }
   wr.tile_end = int32_t(tiles.size() / 2);
@@ -147,7 +185,46 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     } else {
       if (P.grec.empty()) return "general record missing";
       const int32_t *g = &P.grec[4 * size_t(L)];
-      if (g[0] != os || g[1] != w || g[2] != cs || g[3] != wc) return "general record";
+      if (g[0] != os || g[1] != cs || g[2] != (w | (wc << 16))) return "general record";
+      if (P.gnb[2 * size_t(L)] != (cl >= 0 ? P.own_slot[cl] : -1) || P.gnb[2 * size_t(L) + 1] != (pl >= 0 ? P.cslot[pl] : -1))
+        return "neighbour slots";
+      // the child level's in-arc lists hold exactly this level's arcs into it
+      if (wc > 0) {
+        const int64_t rb = g[3];
+        if (rb < 0 || rb + wc >= int64_t(P.rbeg.size())) return "in-arc base";
+        std::vector<int32_t> seen0(size_t(w), 0), seen1(size_t(w), 0);
+        int64_t cnt = 0;
+        if (P.rin.size() != P.rbeg.size()) return "packed in-arcs";
+        for (int32_t v = 0; v < wc; ++v) {
+          const int64_t b0 = P.rbeg[size_t(rb + v)], b1 = P.rbeg[size_t(rb + v + 1)];
+          if (b0 < 0 || b1 < b0 || b1 > int64_t(P.rarc.size())) return "in-arc range";
+          const uint32_t pk = P.rin[size_t(rb + v)];
+          if (b1 - b0 > 2 || b1 == b0) {
+            if (pk != kManyInArcs) return "packed in-arcs";
+          } else if ((pk & 0xFFFFu) != P.rarc[size_t(b0)] ||
+                     (pk >> 16) != (b1 - b0 > 1 ? uint32_t(P.rarc[size_t(b0 + 1)]) : kNoArc16)) {
+            return "packed in-arcs";
+          }
+          for (int64_t q = b0; q < b1; ++q) {
+            const uint32_t a = P.rarc[size_t(q)];
+            const int32_t u = int32_t(a & (kInArcHi - 1u));
+            if (u >= w) return "in-arc source";
+            const uint32_t code = P.garcs[size_t(os + u)];
+            const uint32_t ch = (a & kInArcHi) ? code >> 16 : code & 0xFFFFu;
+            if (int32_t(ch) != v) return "in-arc target";
+            if (((a & kInArcHi) ? seen1 : seen0)[u]++) return "in-arc repeated";
+            ++cnt;
+          }
+        }
+        int64_t live = 0;
+        for (int32_t u = 0; u < w; ++u) {
+          const uint32_t code = P.garcs[size_t(os + u)];
+          live += ((code & 0xFFFFu) < kTop) + ((code >> 16) < kTop);
+        }
+        if (cnt != live) return "in-arc count";
+      } else if (g[3] != -1) {
+        return "in-arc base";
+      }
     }
     if (((meta & kMetaRootBit) != 0) != (level[L] == 0)) return "root flag";
     const uint32_t pos = (meta >> kMetaPosShift) & kMetaField, len = (meta >> kMetaLenShift) & kMetaField;
@@ -164,7 +241,10 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
       for (int big = 0; big < 2; ++big) {
         const auto &tiles = pass ? (big ? P.bwd_big : P.bwd_tiles) : (big ? P.fwd_big : P.fwd_tiles);
         for (int32_t t = big ? wr.big_begin : wr.tile_begin; t < (big ? wr.big_end : wr.tile_end); ++t) {
-          const int64_t p0 = tiles[2 * size_t(t)], p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          const uint32_t w0 = uint32_t(tiles[2 * size_t(t)]);
+          const int64_t p0 = big ? int64_t(w0) : int64_t(w0 & kTilePosMask);
+          const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          if (big && (p0 >> kTileClsShift)) return "big tile start";
           const int64_t cap = big ? kBigMax : kTile;
           if (p1 <= p0 || p1 - p0 > cap || p0 < 0 || p1 > I) return "tile bounds";
           for (int64_t p = p0; p < p1; ++p) {
@@ -179,6 +259,11 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
             }
             const uint32_t meta = P.meta[L];
             if (wr.narrow_only && ((meta >> kMetaWidthShift) & 3u) == 0u) return "narrow-only wave holds a wide level";
+            if (((meta >> kMetaWidthShift) & 3u) == 0u) {
+              const int32_t mw = std::max(ownw[L], childw[L]);
+              const uint32_t need = mw <= 8 ? 0u : (mw <= 32 ? 1u : (mw <= 128 ? 2u : 3u));
+              if ((w0 >> kTileClsShift) < need) return "tile width class";
+            }
             const int64_t head = p - int64_t((meta >> kMetaPosShift) & kMetaField);
             if (nj > kTile || head < p0 || head + nj > p1) return "segment leaves its tile";
           }
@@ -211,6 +296,10 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   P.n = n;
   P.m = m;
   P.hist_cap = opt.hist_cap > 0 ? opt.hist_cap : 4096;
+  if (opt.tile_work < 0) return set_error(BDDMP_INVALID_ARG, "negative tile_work");
+  if (opt.tile_work > 0) P.tile_work = opt.tile_work;
+  if (opt.tiling && !parse_groups(opt.tiling, P.gsel))
+    return set_error(BDDMP_INVALID_ARG, "tiling must be four values, each 0 or a power of two up to 64, e.g. \"0,16,64,64\"");
   P.cost = p.cost;
 
   // processing order
@@ -282,7 +371,8 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   P.N = P.canon_node[m];
   if (opt.node_budget > 0 && P.N > opt.node_budget)
     return set_error(BDDMP_BDD_TOO_LARGE, "total nodes " + std::to_string(P.N) + " exceed the node budget");
-  if (P.N >= INT32_MAX || P.I >= INT32_MAX) return set_error(BDDMP_BDD_TOO_LARGE, "more than 2^31 nodes or incidences");
+  if (P.N >= INT32_MAX || P.I >= int64_t(kTilePosMask))
+    return set_error(BDDMP_BDD_TOO_LARGE, "more than 2^31 nodes or 2^29 incidences");
   const int64_t I = P.I;
   for (int32_t j = 0; j < m; ++j) {
     if (P.row_shape[j] < 0) continue;
@@ -477,14 +567,46 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.meta[Lq] = meta;
   }
   if (P.n_general) {
+    // general records for every layer (a general level's neighbours read them too), and for each
+    // general layer with a child level the in-arc lists of that child level: the pull form of the
+    // forward step (Alg. "Forward BDD update step" takes the minimum over in-arcs)
     P.grec.assign(4 * size_t(I), 0);
+    P.gnb.assign(2 * size_t(I), -1);
     for (int64_t Lq = 0; Lq < I; ++Lq) {
-      P.grec[4 * size_t(Lq) + 0] = int32_t(P.own_slot[Lq]);
-      P.grec[4 * size_t(Lq) + 1] = ownw[Lq];
-      P.grec[4 * size_t(Lq) + 2] = int32_t(P.cslot[Lq]);
-      P.grec[4 * size_t(Lq) + 3] = childw[Lq];
+      if (P.child[Lq] >= 0) P.gnb[2 * size_t(Lq)] = int32_t(P.own_slot[P.child[Lq]]);
+      if (P.parent[Lq] >= 0) P.gnb[2 * size_t(Lq) + 1] = int32_t(P.cslot[P.parent[Lq]]);
+    }
+    std::vector<std::vector<uint16_t>> lists;
+    for (int64_t Lq = 0; Lq < I; ++Lq) {
+      int32_t *g = &P.grec[4 * size_t(Lq)];
+      g[0] = int32_t(P.own_slot[Lq]);
+      g[1] = int32_t(P.cslot[Lq]);
+      g[2] = ownw[Lq] | (childw[Lq] << 16);
+      g[3] = -1;
+      const bool narrow = ((P.meta[Lq] >> kMetaWidthShift) & 3u) != 0u;
+      if (narrow || childw[Lq] == 0) continue;
+      g[3] = int32_t(P.rbeg.size());
+      lists.assign(size_t(childw[Lq]), {});
+      for (int32_t u = 0; u < ownw[Lq]; ++u) {
+        const uint32_t a = P.garcs[size_t(P.own_slot[Lq] + u)];
+        if ((a & 0xFFFFu) < kTop) lists[a & 0xFFFFu].push_back(uint16_t(u));
+        if ((a >> 16) < kTop) lists[a >> 16].push_back(uint16_t(uint32_t(u) | kInArcHi));
+      }
+      for (const auto &li : lists) {
+        P.rbeg.push_back(int32_t(P.rarc.size()));
+        P.rarc.insert(P.rarc.end(), li.begin(), li.end());
+        P.rin.push_back(li.size() > 2 ? kManyInArcs
+                                      : (li.size() > 0 ? li[0] : kNoArc16) | ((li.size() > 1 ? li[1] : kNoArc16) << 16));
+      }
+      P.rbeg.push_back(int32_t(P.rarc.size()));
+      P.rin.push_back(kManyInArcs);
+      if (P.rarc.size() >= size_t(INT32_MAX)) return set_error(BDDMP_BDD_TOO_LARGE, "too many in-arcs");
     }
   }
+  // general-level work per variable (own plus child nodes of its general layers), for the tiler
+  std::vector<int64_t> wwork(size_t(n), 0);
+  for (int64_t Lq = 0; Lq < I; ++Lq)
+    if (((P.meta[Lq] >> kMetaWidthShift) & 3u) == 0u) wwork[P.layer_var[Lq]] += ownw[Lq] + childw[Lq];
   P.root_slot.assign(size_t(m), -1);
   P.bdd_canon_off.assign(size_t(m) + 1, 0);
   for (int32_t j = 0; j < m; ++j) {
@@ -508,7 +630,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       }
   };
   for (int32_t t = 1; t <= P.Df; ++t) {
-    tile_pass(fw[t], P.var_nj, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
+    tile_pass(fw[t], P.var_nj, wwork, P.tile_work, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
     P.fwd_waves[t - 1].list = 0;
     wave_work(fw[t], P.fwd_waves[t - 1]);
     for (int32_t i : fw[t]) pos += P.var_nj[i];
@@ -527,7 +649,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         if (P.bwd_list[pos] != P.bwd_list[w0] + (pos - w0)) contig = false;
       }
     WaveRange &wr = P.bwd_waves[t - 1];
-    tile_pass(bw[t], P.var_nj, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big, wr);
+    tile_pass(bw[t], P.var_nj, wwork, P.tile_work, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big, wr);
     wr.list = contig ? 0 : 1;
     wave_work(bw[t], wr);
     P.bwd_contiguous = P.bwd_contiguous && contig;
@@ -545,6 +667,23 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       if (roots) P.bwd_tiles[2 * size_t(t) + 1] = int32_t(uint32_t(P.bwd_tiles[2 * size_t(t) + 1]) | kTileRootBit);
     }
   P.n_lbpart = int64_t(kTile / 64) * int64_t(P.bwd_tiles.size() / 2) + int64_t(P.bwd_big.size() / 2);
+  // width class of each normal tile in the top bits of its start
+  for (int pass = 0; pass < 2; ++pass) {
+    auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;
+    const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+    for (const WaveRange &wr : waves)
+      for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+        int32_t mw = 0;
+        const int64_t p1 = int64_t(uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit);
+        for (int64_t q = tiles[2 * size_t(t)]; q < p1; ++q) {
+          const int64_t Lq = (pass && wr.list) ? P.bwd_list[size_t(q)] : q;
+          if (((P.meta[Lq] >> kMetaWidthShift) & 3u) == 0u) mw = std::max({mw, ownw[Lq], childw[Lq]});
+        }
+        const uint32_t cls = mw <= 8 ? 0u : (mw <= 32 ? 1u : (mw <= 128 ? 2u : 3u));
+        tiles[2 * size_t(t)] = int32_t(uint32_t(tiles[2 * size_t(t)]) | (cls << kTileClsShift));
+        if (mw > 0) P.class_tiles[cls]++;
+      }
+  }
 
   P.lb_const = 0.0;
   for (int32_t i = 0; i < n; ++i)
@@ -587,6 +726,10 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.mbc = take(4 * size_t(P.Sc) + 16);
   A.garcs = take(4 * S);
   A.grec = take(4 * P.grec.size());
+  A.gnb = take(4 * P.gnb.size());
+  A.rbeg = take(4 * P.rbeg.size());
+  A.rin = take(4 * P.rin.size());
+  A.rarc = take(2 * P.rarc.size());
   A.canon_of = take(4 * In);
   A.layer_of = take(4 * In);
   A.layer_var = take(4 * In);

@@ -21,6 +21,10 @@ int32_t solver_min_marginals(Solver &S, float *m0, float *m1);
 int32_t solver_get_lambda(Solver &S, float *lam);
 int32_t solver_set_lambda(Solver &S, const float *lam);
 int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj, int64_t *nviol);
+int32_t solver_set_graphs(Solver &S, int32_t enable);
+int32_t solver_set_groups(Solver &S, const int32_t *lanes);
+int32_t solver_get_groups(const Solver &S, int32_t *lanes);
+int32_t solver_autotune(Solver &S, int32_t iters, int32_t *lanes);
 int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out);
 void solver_destroy(Solver *S);
 

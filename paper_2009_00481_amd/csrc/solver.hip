@@ -23,8 +23,18 @@ struct Solver {
   char *arena = nullptr;
   hipStream_t stream = nullptr;
   Dev D{};
-  int64_t n_hist = 0;  // bounds recorded so far
+  int64_t n_hist = 0;  // bounds recorded so far (the device counter holds the same count)
   int64_t iters = 0;
+  // one update iteration captured as a HIP graph and replayed by iterate (the kernel arguments,
+  // including the group selection, are baked in: a change of D.gsel re-captures)
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint32_t graph_gsel = 0;
+  ~Solver() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 namespace {
@@ -71,48 +81,82 @@ struct Timer {
 };
 
 // One pass: every wave in order, one launch per wave (plus one for the wave's big tiles if any).
-int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev) {
+int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipStream_t st) {
   const Plan &P = *S.plan;
   const auto &waves = dir == kFwd ? P.fwd_waves : P.bwd_waves;
   Timer tm{ev};
-  if (int32_t rc = tm.start(S.stream, dir)) return rc;
+  if (int32_t rc = tm.start(st, dir)) return rc;
   for (const WaveRange &wr : waves) {
     const int nt = wr.tile_end - wr.tile_begin;
     const int nb = wr.big_end - wr.big_begin;
     const bool list = dir == kBwd && wr.list;
     if (nt > 0)
-      if (int32_t rc = launched(launch_wave(dir, mode, wr.narrow_only, list, nt, wr.tile_begin, S.D, S.stream),
-                                "wave kernel"))
+      if (int32_t rc = launched(launch_wave(dir, mode, wr.narrow_only, list, nt, wr.tile_begin, S.D, st), "wave kernel"))
         return rc;
     if (nb > 0)
-      if (int32_t rc = launched(launch_wave_big(dir, mode, list, nb, wr.big_begin, S.D, S.stream), "wave kernel (big)"))
+      if (int32_t rc = launched(launch_wave_big(dir, mode, list, nb, wr.big_begin, S.D, st), "wave kernel (big)"))
         return rc;
   }
-  return tm.stop(S.stream, int(waves.size()));
+  return tm.stop(st, int(waves.size()));
 }
 
-// the bound of the backward sweep just run, from its per-tile partials
-int32_t record_lb(Solver &S, std::vector<EventPair> *ev) {
+// the bound of the backward sweep just run, from its per-tile partials, into the history slot the
+// device counter names (the caller advances the host count S.n_hist)
+int32_t enqueue_lb(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
   const Plan &P = *S.plan;
   Timer tm{ev};
-  if (int32_t rc = tm.start(S.stream, 2)) return rc;
-  const int slot = int(S.n_hist % P.hist_cap);
-  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart), P.lb_const, slot, S.stream), "bound reduction"))
-    return rc;
-  if (int32_t rc = tm.stop(S.stream, 1)) return rc;
+  if (int32_t rc = tm.start(st, 2)) return rc;
+  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart), P.lb_const, st), "bound reduction")) return rc;
+  return tm.stop(st, 1);
+}
+
+int32_t initial_sweep(Solver &S) {
+  if (int32_t rc = run_pass(S, kBwd, kNoUpdate, nullptr, S.stream)) return rc;
+  if (int32_t rc = enqueue_lb(S, nullptr, S.stream)) return rc;
   S.n_hist++;
   return BDDMP_OK;
 }
 
-int32_t initial_sweep(Solver &S) {
-  if (int32_t rc = run_pass(S, kBwd, kNoUpdate, nullptr)) return rc;
-  return record_lb(S, nullptr);
+// enqueue one iteration (forward pass, backward pass, bound) on st
+int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
+  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st)) return rc;
+  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st)) return rc;
+  return enqueue_lb(S, ev, st);
 }
 
 int32_t one_iteration(Solver &S, std::vector<EventPair> *ev) {
-  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev)) return rc;
-  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev)) return rc;
-  return record_lb(S, ev);
+  if (int32_t rc = enqueue_iteration(S, ev, S.stream)) return rc;
+  S.n_hist++;
+  S.iters++;
+  return BDDMP_OK;
+}
+
+void drop_graph(Solver &S) {
+  if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
+  S.gexec = nullptr;
+}
+
+// Captures one iteration's launches on a private stream into an executable graph.
+int32_t capture_iteration(Solver &S) {
+  drop_graph(S);
+  if (!S.cap) HIP_TRY(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  HIP_TRY(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  const int32_t rc = enqueue_iteration(S, nullptr, S.cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(S.cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+  const hipError_t ei = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    S.gexec = nullptr;
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
+  S.graph_gsel = S.D.gsel;
+  return BDDMP_OK;
 }
 
 }  // namespace
@@ -138,6 +182,11 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.mbc = reinterpret_cast<float *>(b + A.mbc);
   D.garcs = reinterpret_cast<const uint32_t *>(b + A.garcs);
   D.grec = P.grec.empty() ? nullptr : reinterpret_cast<const int4 *>(b + A.grec);
+  D.gnb = reinterpret_cast<const int2 *>(b + A.gnb);
+  D.rbeg = reinterpret_cast<const int32_t *>(b + A.rbeg);
+  D.rin = reinterpret_cast<const uint32_t *>(b + A.rin);
+  D.rarc = reinterpret_cast<const uint16_t *>(b + A.rarc);
+  D.gsel = P.gsel;
   D.canon_of = reinterpret_cast<const int32_t *>(b + A.canon_of);
   D.layer_of = reinterpret_cast<const int32_t *>(b + A.layer_of);
   D.layer_var = reinterpret_cast<const int32_t *>(b + A.layer_var);
@@ -160,6 +209,8 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.scal = reinterpret_cast<double *>(b + A.scal);
   D.out0 = D.out1 = nullptr;
   D.n_bwd_tiles = int32_t(P.bwd_tiles.size() / 2);
+  D.hist_n = reinterpret_cast<long long *>(b + A.scal + 64);
+  D.hist_cap = P.hist_cap;
   D.inst_row = reinterpret_cast<const int32_t *>(b + A.inst_row);
   D.inst_lb = reinterpret_cast<double *>(b + A.inst_lb);
 
@@ -173,6 +224,10 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.parent, P.parent.data(), 4 * P.parent.size()),
       up(A.garcs, P.garcs.data(), 4 * P.garcs.size()),
       up(A.grec, P.grec.data(), 4 * P.grec.size()),
+      up(A.gnb, P.gnb.data(), 4 * P.gnb.size()),
+      up(A.rbeg, P.rbeg.data(), 4 * P.rbeg.size()),
+      up(A.rin, P.rin.data(), 4 * P.rin.size()),
+      up(A.rarc, P.rarc.data(), 2 * P.rarc.size()),
       up(A.canon_of, P.canon_of.data(), 4 * P.canon_of.size()),
       up(A.layer_of, P.layer_of.data(), 4 * P.layer_of.size()),
       up(A.layer_var, P.layer_var.data(), 4 * P.layer_var.size()),
@@ -212,16 +267,31 @@ int32_t solver_reset(Solver &S) {
   if (int32_t rc = launched(launch_fill(S.D.mbc, INFINITY, ncslots, S.stream), "fill")) return rc;
   if (int32_t rc = launched(launch_init_lambda(S.D, int(P.I), S.stream), "init_lambda")) return rc;
   if (int32_t rc = launched(launch_root_zero(S.D, P.m, S.stream), "root_zero")) return rc;
+  if (int32_t rc = launched(launch_set_counter(S.D, S.n_hist, S.stream), "set_counter")) return rc;
   S.iters = 0;
   return initial_sweep(S);
 }
 
 int32_t solver_iterate(Solver &S, int32_t n) {
   if (n < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
-  for (int32_t t = 0; t < n; ++t) {
-    if (int32_t rc = one_iteration(S, nullptr)) return rc;
-    S.iters++;
+  if (S.use_graph && n > 0) {
+    if (!S.gexec || S.graph_gsel != S.D.gsel)
+      if (int32_t rc = capture_iteration(S)) return rc;
+    for (int32_t t = 0; t < n; ++t) {
+      HIP_TRY(hipGraphLaunch(S.gexec, S.stream), "hipGraphLaunch");
+      S.n_hist++;
+      S.iters++;
+    }
+    return BDDMP_OK;
   }
+  for (int32_t t = 0; t < n; ++t)
+    if (int32_t rc = one_iteration(S, nullptr)) return rc;
+  return BDDMP_OK;
+}
+
+int32_t solver_set_graphs(Solver &S, int32_t enable) {
+  S.use_graph = enable != 0;
+  if (!S.use_graph) drop_graph(S);
   return BDDMP_OK;
 }
 
@@ -273,7 +343,7 @@ int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out) {
 int32_t solver_min_marginals(Solver &S, float *m0, float *m1) {
   S.D.out0 = m0;
   S.D.out1 = m1;
-  const int32_t rc = run_pass(S, kFwd, kExtract, nullptr);
+  const int32_t rc = run_pass(S, kFwd, kExtract, nullptr, S.stream);
   S.D.out0 = S.D.out1 = nullptr;
   return rc;
 }
@@ -305,31 +375,84 @@ int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj
   return BDDMP_OK;
 }
 
+int32_t solver_set_groups(Solver &S, const int32_t *lanes) {
+  if (!lanes) return set_error(BDDMP_INVALID_ARG, "null lanes");
+  uint32_t g = 0;
+  for (int c = 0; c < kWidthClasses; ++c) {
+    uint32_t code = 0;
+    if (!gsel_code(lanes[c], code)) return set_error(BDDMP_INVALID_ARG, "lanes must be 0 or powers of two up to 64");
+    g |= code << (4 * c);
+  }
+  S.D.gsel = g;
+  return BDDMP_OK;
+}
+
+int32_t solver_get_groups(const Solver &S, int32_t *lanes) {
+  if (!lanes) return set_error(BDDMP_INVALID_ARG, "null lanes");
+  for (int c = 0; c < kWidthClasses; ++c) {
+    const uint32_t code = (S.D.gsel >> (4 * c)) & 0xFu;
+    lanes[c] = code == kGselFlat ? 0 : 1 << code;
+  }
+  return BDDMP_OK;
+}
+
+// Coordinate search over the general-layer path: for each width class that has tiles, time iters
+// iterations with the node-parallel path and with groups of every power of two from 1 to 64 lanes
+// (the other classes at their current choice) and keep the fastest. Every choice computes the same values (min is exact), so only
+// time differs; the solver advances by the iterations run.
+int32_t solver_autotune(Solver &S, int32_t iters, int32_t *lanes) {
+  const Plan &P = *S.plan;
+  if (iters < 1) return set_error(BDDMP_INVALID_ARG, "iters must be positive");
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+  int32_t rc = BDDMP_OK;
+  for (int c = 0; c < kWidthClasses && !rc; ++c) {
+    if (!P.class_tiles[c]) continue;
+    uint32_t best_lg = (S.D.gsel >> (4 * c)) & 0xFu;
+    float best = INFINITY;
+    for (uint32_t lg : {kGselFlat, 0u, 1u, 2u, 3u, 4u, 5u, 6u}) {
+      if (rc) break;
+      S.D.gsel = (S.D.gsel & ~(0xFu << (4 * c))) | (lg << (4 * c));
+      hipError_t e = hipEventRecord(a, S.stream);
+      if (e == hipSuccess) rc = solver_iterate(S, iters);
+      if (e == hipSuccess) e = hipEventRecord(b, S.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess && !rc) rc = hip_fail(e, "autotune timing");
+      if (!rc && ms < best) {
+        best = ms;
+        best_lg = lg;
+      }
+    }
+    S.D.gsel = (S.D.gsel & ~(0xFu << (4 * c))) | (best_lg << (4 * c));
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  return lanes ? solver_get_groups(S, lanes) : BDDMP_OK;
+}
+
 int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
   const Plan &P = *S.plan;
   std::vector<EventPair> ev;
   ev.reserve(size_t(n) * 3);
   int32_t rc = BDDMP_OK;
-  for (int32_t t = 0; t < n && !rc; ++t) {
-    rc = one_iteration(S, &ev);
-    S.iters++;
-  }
+  for (int32_t t = 0; t < n && !rc; ++t) rc = one_iteration(S, &ev);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (!rc) {
     HIP_TRY(hipEventCreate(&t0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&t1), "hipEventCreate");
     HIP_TRY(hipEventRecord(t0, S.stream), "hipEventRecord");
-    for (int32_t t = 0; t < n && !rc; ++t) {
-      rc = one_iteration(S, nullptr);
-      S.iters++;
-    }
+    rc = solver_iterate(S, n);
     HIP_TRY(hipEventRecord(t1, S.stream), "hipEventRecord");
   }
   const hipError_t se = hipStreamSynchronize(S.stream);
   bddmp_kernel_times r{};
   for (const EventPair &e : ev) {
     float ms = 0.0f;
-    if (!rc && se == hipSuccess) hipEventElapsedTime(&ms, e.a, e.b);
+    if (!rc && se == hipSuccess) (void)hipEventElapsedTime(&ms, e.a, e.b);
     if (e.cls == 0) {
       r.fwd_ms += ms;
       r.fwd_launches += e.launches;
@@ -340,16 +463,16 @@ int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
       r.lb_ms += ms;
       r.lb_launches += e.launches;
     }
-    hipEventDestroy(e.a);
-    hipEventDestroy(e.b);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
   if (!rc && se == hipSuccess && t0) {
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventElapsedTime(&ms, t0, t1);
     r.iter_ms = n ? ms / n : 0.0;
   }
-  if (t0) hipEventDestroy(t0);
-  if (t1) hipEventDestroy(t1);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
   if (rc) return rc;
   if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
   const double pass_bytes = 20.0 * double(P.N) + 8.0 * double(P.I);

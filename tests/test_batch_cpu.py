@@ -204,3 +204,13 @@ def test_batch_config_mix():
     again = I.batch_config(6, p_range=(4, 9), d_range=(120, 260))
     for a, b in zip(insts, again):
         assert np.array_equal(a.col, b.col) and np.array_equal(a.cost, b.cost)
+
+
+def test_tiling_option():
+    q = I.tomography(6, seed=0)
+    for good in ("4,16,64,64", "1,1,1,1", "64,32,2,8", "0,0,0,0", "0,16,0,64"):
+        B.Plan(B.Problem.from_ilp(q), tiling=good)
+    for bad in ("3,16,64,64", "4,16,64", "4,16,64,64,1", "4,16,128,64", "a,b,c,d", "4,16,64,64x", "", "-1,0,0,0"):
+        with pytest.raises(B.BddmpError) as e:
+            B.Plan(B.Problem.from_ilp(q), tiling=bad)
+        assert e.value.code == -1, bad

@@ -11,7 +11,11 @@ relaxed and marginalised once per pass). The roofline object prices the dominant
 algorithmic bytes (20 per node and 8 per incidence per pass) against MI355X HBM peak; cpu_baseline
 is the fp64 CPU oracle on the same instance, one thread, on a bounded sample of iterations.
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload potts256x256_L8]
+batched_vs_plain: the batched workload (256 tomography and tracking instances of uneven size) in
+one schedule against the same instances run one after another through their own plans; a sample of
+instances is compared bitwise.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload potts256x256_L8] [--no-batched]
 """
 import argparse
 import json
@@ -67,6 +71,74 @@ def committed_traffic(workload: str):
     return None
 
 
+def batched_vs_plain(args, B, I, torch):
+    """The batched workload (tomography and tracking instances of uneven size) solved in one
+    schedule against the same instances solved one after another through their own plans."""
+    import numpy as np
+
+    n = args.batch_instances
+    t = time.perf_counter()
+    insts = I.batch_config(n)
+    gen_s = time.perf_counter() - t
+    probs = [B.Problem.from_ilp(q) for q in insts]
+    t = time.perf_counter()
+    bp = B.Plan(probs)
+    plan_s = time.perf_counter() - t
+    st = bp.stats
+    log(f"[bench] batched: {n} instances, nodes={st.n_nodes} incidences={st.n_incidences} "
+        f"waves={st.waves_fwd}+{st.waves_bwd} plan {plan_s:.1f}s")
+    bs = B.Solver(bp)
+    bs.iterate(1)
+    T = args.batch_iters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.iterate(T)
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) * 1e3 / T
+    # bitwise check on a sample: the same iterations from the start, batched and plain
+    Tc = 5
+    bs.reset()
+    bs.iterate(Tc)
+    lam_b = bs.get_lambda().cpu().numpy()
+    _, _, inc_off = bp.instances()
+    sample = sorted(set([0, 1, 2, 3, n - 2, n - 1]) & set(range(n)))
+    del bs
+    torch.cuda.empty_cache()
+    plain_ms, plain_plan_s, equal = 0.0, 0.0, 0
+    kp = args.batch_plain_iters
+    for k, pr in enumerate(probs):
+        tp = time.perf_counter()
+        p = B.Plan(pr)
+        plain_plan_s += time.perf_counter() - tp
+        s = B.Solver(p)
+        s.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(kp)
+        torch.cuda.synchronize()
+        plain_ms += (time.perf_counter() - t0) * 1e3 / kp
+        if k in sample:
+            s.reset()
+            s.iterate(Tc)
+            lam_p = s.get_lambda().cpu().numpy()
+            equal += int(np.array_equal(lam_p, lam_b[inc_off[k]:inc_off[k + 1]]))
+        del s, p
+    torch.cuda.empty_cache()
+    arcs = 2.0 * st.n_arcs_live
+    model = 40.0 * st.n_nodes + 16.0 * st.n_incidences
+    return {"workload": f"batch{n}: tomography P~U{{32..128}} (even positions) + tracking D~U{{200..2000}}",
+            "instances": n, "n_nodes": int(st.n_nodes), "n_incidences": int(st.n_incidences),
+            "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
+            "batched_ms_per_iter": batched_ms, "plain_ms_per_iter": plain_ms,
+            "speedup": plain_ms / batched_ms,
+            "batched_arc_updates_per_s": arcs / (batched_ms * 1e-3),
+            "plain_arc_updates_per_s": arcs / (plain_ms * 1e-3),
+            "batched_model_gbps": model / (batched_ms * 1e-3) / 1e9,
+            "timed_iters": {"batched": T, "plain_per_instance": kp},
+            "bitwise_equal_instances": f"{equal}/{len(sample)} sampled after {Tc} iterations",
+            "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +149,10 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--batch-plain-iters", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -204,6 +280,13 @@ def main():
                "s_per_iter": cpu_s / done}
         del o
 
+    batched = None
+    if not args.no_batched:
+        del s
+        torch.cuda.empty_cache()
+        batched = batched_vs_plain(args, B, I, torch)
+        log(f"[bench] batched vs plain: {batched['batched_ms_per_iter']:.2f} vs {batched['plain_ms_per_iter']:.1f} ms/iter")
+
     rec = {
         "metric": METRIC, "value": value, "unit": "arc-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -217,6 +300,7 @@ def main():
         "primal_obj": obj, "primal_violated_rows": int(nviol),
         "host_build_s": {"generate": gen_s, "plan": plan_s, "bind_upload": bind_s},
         "roofline": roofline, "cpu_baseline": cpu,
+        "batched_vs_plain": batched,
     }
     print(json.dumps(rec), flush=True)
 

@@ -295,8 +295,8 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   // LDS of the general-layer paths (one element in narrow-only instantiations)
   __shared__ std::conditional_t<NARROW_ONLY, int, GenTile> s_g;
   __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap], s_fu[NARROW_ONLY ? 1 : kFlatCap];
-  // node -> compact layer index of the flat path (own and next-level nodes)
-  __shared__ uint8_t s_mo[NARROW_ONLY ? 1 : kFlatCap], s_mc[NARROW_ONLY ? 1 : kFlatCap];
+  // flat path: the layer holding the first node of each 64-node chunk (own and next-level nodes)
+  __shared__ uint8_t s_cko[NARROW_ONLY ? 1 : kFlatCap / 64], s_ckc[NARROW_ONLY ? 1 : kFlatCap / 64];
   const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
   const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
   const uint32_t w0 = uint32_t(tiles[2 * tix]);
@@ -380,58 +380,24 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     mode = int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
     flat = mode == int(kFlat) && TW <= kFlatCap && TC <= kFlatCap;
     G = mode == int(kFlat) ? 64 : (1 << mode);
-    if (flat) {
-      // node -> layer maps: each layer marks its first own (next-level) node, then a prefix max
-      // over the nodes (layers are in ascending node order)
-#pragma unroll
-      for (int r = 0; r < kFlatR; ++r) {
-        s_mo[s * kFlatR + r] = 0;
-        s_mc[s * kFlatR + r] = 0;
-      }
+    if (flat && gen) {
+      // chunk table: this layer holds the first node of chunks ceil(wo/64) .. floor((wo+w-1)/64)
+      const int o0 = T.wo[myk], c0 = T.co[myk];
+      for (int c = (o0 + 63) >> 6; c <= (o0 + w - 1) >> 6; ++c) s_cko[c] = uint8_t(myk);
+      if (wc > 0)
+        for (int c = (c0 + 63) >> 6; c <= (c0 + wc - 1) >> 6; ++c) s_ckc[c] = uint8_t(myk);
     }
     __syncthreads();
     if (flat) {
-      if (gen) {
-        s_mo[T.wo[myk]] = uint8_t(myk);
-        if (wc > 0) s_mc[T.co[myk]] = uint8_t(myk);
-      }
-      __syncthreads();
-      int mo = 0, mc = 0;
+      // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
+      // t = s + r * kTile; slots past the tile's nodes are skipped per wavefront.
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
-        mo = max(mo, int(s_mo[s * kFlatR + r]));
-        mc = max(mc, int(s_mc[s * kFlatR + r]));
-      }
-      for (int o = 1; o < 64; o <<= 1) {
-        const int to = __shfl_up(mo, o, 64), tc = __shfl_up(mc, o, 64);
-        if (lane >= o) {
-          mo = max(mo, to);
-          mc = max(mc, tc);
-        }
-      }
-      if (lane == 63) s_wcnt[wv] = mo | (mc << 16);
-      __syncthreads();
-      int po = __shfl_up(mo, 1, 64), pc = __shfl_up(mc, 1, 64);
-      if (lane == 0) po = pc = 0;
-      for (int q = 0; q < wv; ++q) {
-        po = max(po, s_wcnt[q] & 0xFFFF);
-        pc = max(pc, s_wcnt[q] >> 16);
-      }
-#pragma unroll
-      for (int r = 0; r < kFlatR; ++r) {
-        po = max(po, int(s_mo[s * kFlatR + r]));
-        pc = max(pc, int(s_mc[s * kFlatR + r]));
-        s_mo[s * kFlatR + r] = uint8_t(po);
-        s_mc[s * kFlatR + r] = uint8_t(pc);
-      }
-      __syncthreads();
-      // own nodes: arcs and forward messages; child nodes: backward messages into LDS
-#pragma unroll
-      for (int r = 0; r < kFlatR; ++r) {
-        const int t = s + r * kTile;
         kr[r] = -1;
-        if (t < TW) {
-          const int k = s_mo[t];
+        const int t = s + r * kTile;
+        if (r * kTile < TW && t < TW) {
+          int k = s_cko[t >> 6];
+          while (k + 1 < ngen && T.wo[k + 1] <= t) ++k;
           const int u = t - T.wo[k];
           kr[r] = k;
           ar[r] = D.garcs[T.os[k] + u];
@@ -441,38 +407,38 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         const int t = s + r * kTile;
-        if (t < TC) {
-          const int k = s_mc[t];
+        if (r * kTile < TC && t < TC) {
+          int k = s_ckc[t >> 6];
+          while (k + 1 < ngen && T.co[k + 1] <= t) ++k;
           s_cb[t] = D.mbc[T.cs[k] + (t - T.co[k])];
         }
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
+        if (r * kTile >= TW) break;
         const int k = kr[r];
-        float m0 = INFINITY, m1 = INFINITY;
+        unsigned o0 = ord_of(INFINITY), o1 = o0;
         if (k >= 0) {
           const int c0 = T.co[k];
           const float lam0 = T.lam[k];
-          m0 = fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu);
-          m1 = (fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16);
+          o0 = ord_of(fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu));
+          o1 = ord_of((fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16));
           s_fu[s + r * kTile] = fr[r];
         }
         // a wavefront whose 64 nodes all belong to one layer reduces first (one LDS atomic
-        // instead of 64 on the same word); min is exact, so the order does not matter
+        // instead of 64 on one word); integer min of the order-preserving codes is exact
         const int k0 = __shfl(k, 0, 64), k63 = __shfl(k, 63, 64);
         if (k0 == k63 && k0 >= 0) {
-          for (int o = 32; o > 0; o >>= 1) {
-            m0 = fminf(m0, __shfl_xor(m0, o, 64));
-            m1 = fminf(m1, __shfl_xor(m1, o, 64));
-          }
+          o0 = __reduce_min_sync(~0ull, o0);
+          o1 = __reduce_min_sync(~0ull, o1);
           if (lane == 0) {
-            atomicMin(&T.m0[k0], ord_of(m0));
-            atomicMin(&T.m1[k0], ord_of(m1));
+            atomicMin(&T.m0[k0], o0);
+            atomicMin(&T.m1[k0], o1);
           }
         } else if (k >= 0) {
-          atomicMin(&T.m0[k], ord_of(m0));
-          atomicMin(&T.m1[k], ord_of(m1));
+          atomicMin(&T.m0[k], o0);
+          atomicMin(&T.m1[k], o1);
         }
       }
     } else {
@@ -535,8 +501,9 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
 #pragma unroll
         for (int r = 0; r < kFlatR; ++r) {
           const int t = s + r * kTile;
-          if (t < TC) {
-            const int k = s_mc[t];
+          if (r * kTile < TC && t < TC) {
+            int k = s_ckc[t >> 6];
+            while (k + 1 < ngen && T.co[k + 1] <= t) ++k;
             const int osc = T.osc[k];
             if (osc >= 0) {
               const int v = t - T.co[k], f0 = T.wo[k];
@@ -547,6 +514,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
       } else {
 #pragma unroll
         for (int r = 0; r < kFlatR; ++r) {
+          if (r * kTile >= TW) break;
           const int k = kr[r];
           if (k >= 0) {
             const int u = s + r * kTile - T.wo[k], c0 = T.co[k], ps = T.pcs[k];

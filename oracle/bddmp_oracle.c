@@ -793,3 +793,437 @@ long long orc_build_row(int k, const long long *a, int sense, long long b, long 
   free_bdd(&B);
   return nn;
 }
+
+/* ---------------------------------------------------------------------------
+ * Smoothed variant (App. "Smoothing"). The (+, min) algebra of the steps becomes the marginal
+ * log-sum-exp algebra of Table "algebras", kept in the log domain: min(a, b) is replaced by the
+ * soft minimum smin(a, b) = -alpha log(exp(-a/alpha) + exp(-b/alpha)), so the forward, backward
+ * and marginal values are -alpha log of the path sums of exp(-cost/alpha). The update is eq.
+ * "mma-update" on these marginal values. Readings (design notes): the bound adds
+ * smin(0, c_i) for each variable in no row (its two assignments); several arguments fold left in
+ * the order of the min-plus code. When rows force the variable (an infinite difference), the
+ * smoothed block maximum is not attained, and the min-plus forced-row rule can lower the smoothed
+ * bound (by up to alpha log 2 per row it moves); instead only the rows whose move raises the bound
+ * hand their difference to the forced rows: with rows forcing x_i = 1 those with d_k > 0, with
+ * rows forcing x_i = 0 those with d_k < 0 (each then has d_k = 0; the forced rows share the sum).
+ *
+ * The derivative of the smoothed bound after T iterations with respect to the costs is computed
+ * by reverse accumulation: lambda after each iteration is kept (an iteration is a function of
+ * lambda alone, because the backward messages it starts from are the backward sweep of lambda),
+ * each iteration is recomputed from its checkpoint, then its backward pass and its forward pass
+ * are undone in reverse order, every step passing adjoints back through the soft-minimum weights
+ * exp(-(argument - result)/alpha), which are the derivatives of smin.
+ * ------------------------------------------------------------------------- */
+
+static REAL smin(REAL a, REAL b, double alpha) {
+  REAL lo = a < b ? a : b, hi = a < b ? b : a;
+  if (isinf(hi)) return lo;
+  return (REAL)((double)lo - alpha * log1p(exp(-((double)hi - (double)lo) / alpha)));
+}
+
+/* derivative of s = smin(..., a, ...) with respect to argument a */
+static double sweight(REAL a, REAL s, double alpha) {
+  if (isinf(a) || isinf(s)) return 0.0;
+  return exp(-((double)a - (double)s) / alpha);
+}
+
+static REAL child_val(const REAL *mb, const bdd_t *B, int l, int c) {
+  if (c == TOP) return (REAL)0;
+  if (c == BOT) return REAL_INF;
+  return mb[B->first[l + 1] + c];
+}
+
+/* smoothed Alg. "Forward BDD update step" at level l (lam: the diagram's multipliers) */
+static void forward_step_s(const bdd_t *B, const REAL *lam, REAL *mf, int l, double alpha) {
+  if (l == 0) { mf[B->first[0]] = 0; return; }
+  for (int v = B->first[l]; v < B->first[l + 1]; ++v) mf[v] = REAL_INF;
+  for (int u = B->first[l - 1]; u < B->first[l]; ++u) {
+    int c[2] = {B->lo[u], B->hi[u]};
+    for (int beta = 0; beta < 2; ++beta) {
+      if (c[beta] < 0) continue;
+      int v = B->first[l] + c[beta];
+      mf[v] = smin(mf[v], mf[u] + (beta ? lam[l - 1] : (REAL)0), alpha);
+    }
+  }
+}
+
+/* smoothed Alg. "Backward BDD update step" at level l */
+static void backward_step_s(const bdd_t *B, const REAL *lam, REAL *mb, int l, double alpha) {
+  for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+    mb[u] = smin(child_val(mb, B, l, B->lo[u]), child_val(mb, B, l, B->hi[u]) + lam[l], alpha);
+}
+
+/* eq. "marginal-log-sum-exp" at level l through arc values (m_fwd + theta) + m_bwd */
+static void level_marginals_s(const bdd_t *B, const REAL *lam, const REAL *mf, const REAL *mb, int l,
+                              REAL *m0, REAL *m1, double alpha) {
+  REAL best[2] = {REAL_INF, REAL_INF};
+  for (int u = B->first[l]; u < B->first[l + 1]; ++u) {
+    int c[2] = {B->lo[u], B->hi[u]};
+    for (int beta = 0; beta < 2; ++beta) {
+      REAL arc = (mf[u] + (beta ? lam[l] : (REAL)0)) + child_val(mb, B, l, c[beta]);
+      best[beta] = smin(best[beta], arc, alpha);
+    }
+  }
+  *m0 = best[0];
+  *m1 = best[1];
+}
+
+static double lower_bound_s(const orc_state *S, double alpha) {
+  double lb = 0.0;
+  for (int j = 0; j < S->m; ++j)
+    if (S->bdd[j].k) lb += (double)S->bdd[j].mb[S->bdd[j].first[0]];
+  for (int i = 0; i < S->n; ++i)
+    if (S->inc_ptr[i] == S->inc_ptr[i + 1]) lb += (double)smin((REAL)0, (REAL)S->cost[i], alpha);
+  return lb;
+}
+
+/* the smoothed update (forced rows as in the header of this section) */
+static int apply_update_s(orc_state *S, int i, const REAL *d) {
+  int a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+  int nF = 0, pos = 0, neg = 0;
+  for (int q = 0; q < cnt; ++q)
+    if (isinf(d[q])) { ++nF; if (d[q] > 0) pos = 1; else neg = 1; }
+  if (pos && neg) return fail(ORC_CONFLICT, "rows force variable to both values", i);
+  if (nF == 0) return apply_update(S, i, d);
+  REAL moved = 0;
+  for (int q = 0; q < cnt; ++q)
+    if (!isinf(d[q]) && (neg ? d[q] > 0 : d[q] < 0)) moved += d[q];
+  REAL share = moved / (REAL)nF;
+  for (int q = 0; q < cnt; ++q) {
+    bdd_t *B = &S->bdd[S->inc_bdd[a0 + q]];
+    int l = S->inc_lvl[a0 + q];
+    if (isinf(d[q])) B->lam[l] = B->lam[l] + share;
+    else if (neg ? d[q] > 0 : d[q] < 0) B->lam[l] = B->lam[l] - d[q];
+  }
+  return ORC_OK;
+}
+
+static int process_variable_s(orc_state *S, int i, int fwd, double alpha) {
+  int a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+  if (cnt == 0) return ORC_OK;
+  REAL *d = S->dbuf;
+  for (int q = 0; q < cnt; ++q) {
+    bdd_t *B = &S->bdd[S->inc_bdd[a0 + q]];
+    int l = S->inc_lvl[a0 + q];
+    REAL m0, m1;
+    if (fwd) forward_step_s(B, B->lam, B->mf, l, alpha);
+    level_marginals_s(B, B->lam, B->mf, B->mb, l, &m0, &m1, alpha);
+    d[q] = m1 - m0;
+  }
+  int rc = apply_update_s(S, i, d);
+  if (rc != ORC_OK) return rc;
+  if (!fwd)
+    for (int q = 0; q < cnt; ++q) {
+      bdd_t *B = &S->bdd[S->inc_bdd[a0 + q]];
+      backward_step_s(B, B->lam, B->mb, S->inc_lvl[a0 + q], alpha);
+    }
+  return ORC_OK;
+}
+
+static void sweep_s(orc_state *S, double alpha) {
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    for (int l = B->k - 1; l >= 0; --l) backward_step_s(B, B->lam, B->mb, l, alpha);
+  }
+}
+
+static void init_lambda(orc_state *S) {
+  for (int i = 0; i < S->n; ++i) {
+    int cnt = S->inc_ptr[i + 1] - S->inc_ptr[i];
+    for (int q = S->inc_ptr[i]; q < S->inc_ptr[i + 1]; ++q)
+      S->bdd[S->inc_bdd[q]].lam[S->inc_lvl[q]] = (REAL)(S->cost[i] / (double)cnt);
+  }
+}
+
+/* Smoothed initialisation: lambda = c / |J_i|, smoothed backward messages, LB_alpha. */
+int orc_smooth_init(orc_state *S, double alpha) {
+  if (!(alpha > 0)) return fail(ORC_INVALID_ARG, "alpha must be positive", 0);
+  S->flags = 0;
+  init_lambda(S);
+  sweep_s(S, alpha);
+  S->lb = lower_bound_s(S, alpha);
+  S->inited = 2;
+  return ORC_OK;
+}
+
+static int smooth_round(orc_state *S, double alpha) {
+  for (int r = 0; r < S->n; ++r) {
+    int rc = process_variable_s(S, S->order[r], 1, alpha);
+    if (rc) return rc;
+  }
+  for (int r = S->n - 1; r >= 0; --r) {
+    int rc = process_variable_s(S, S->order[r], 0, alpha);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_smooth_iterate(orc_state *S, double alpha, int iters, double *lb_trace) {
+  if (S->inited != 2) return fail(ORC_BAD_STATE, "orc_smooth_init first", 0);
+  for (int t = 0; t < iters; ++t) {
+    int rc = smooth_round(S, alpha);
+    if (rc) return rc;
+    S->lb = lower_bound_s(S, alpha);
+    if (lb_trace) lb_trace[t] = S->lb;
+  }
+  return ORC_OK;
+}
+
+/* Fresh marginal log-sum-exp values at the current multipliers (canonical order). */
+int orc_smooth_marginals(orc_state *S, double alpha, double *m0, double *m1) {
+  if (S->inited != 2) return fail(ORC_BAD_STATE, "orc_smooth_init first", 0);
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    for (int l = 0; l < B->k; ++l) {
+      REAL a, b;
+      forward_step_s(B, B->lam, B->mf, l, alpha);
+      level_marginals_s(B, B->lam, B->mf, B->mb, l, &a, &b, alpha);
+      m0[S->canon[j] + l] = (double)a;
+      m1[S->canon[j] + l] = (double)b;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Per row at the current multipliers, from scratch: E^j (min-plus) and E^j_alpha (smoothed). */
+void orc_row_energies(const orc_state *S, double alpha, double *e, double *e_alpha) {
+  for (int j = 0; j < S->m; ++j) {
+    const bdd_t *B = &S->bdd[j];
+    if (B->k == 0) { e[j] = e_alpha[j] = 0.0; continue; }
+    e[j] = energy_scratch(B);
+    int nn = B->first[B->k];
+    REAL *mb = (REAL *)malloc((size_t)nn * sizeof(REAL));
+    for (int l = B->k - 1; l >= 0; --l) backward_step_s(B, B->lam, mb, l, alpha);
+    e_alpha[j] = (double)mb[B->first[0]];
+    free(mb);
+  }
+}
+
+/* ---- reverse accumulation ---- */
+
+typedef struct {
+  double alpha;
+  const REAL *mf;    /* forward messages the pass used (flat, canonical node order) */
+  const REAL *mb;    /* backward messages the step read (flat) */
+  const REAL *lam0;  /* multipliers before the update (flat, canonical incidence order) */
+  const REAL *lam1;  /* multipliers after the update */
+  double *gmf, *gmb, *glam;
+} rev_t;
+
+static void set_lam(orc_state *S, const double *lam) {
+  for (int j = 0; j < S->m; ++j)
+    for (int l = 0; l < S->bdd[j].k; ++l) S->bdd[j].lam[l] = (REAL)lam[S->canon[j] + l];
+}
+static void get_lam(const orc_state *S, REAL *lam) {
+  for (int j = 0; j < S->m; ++j)
+    for (int l = 0; l < S->bdd[j].k; ++l) lam[S->canon[j] + l] = S->bdd[j].lam[l];
+}
+static void get_msgs(const orc_state *S, REAL *flat, int which) {
+  for (int j = 0; j < S->m; ++j) {
+    const bdd_t *B = &S->bdd[j];
+    if (!B->k) continue;
+    memcpy(flat + S->ncanon[j], which ? B->mb : B->mf, (size_t)B->first[B->k] * sizeof(REAL));
+  }
+}
+
+/* undo the backward step of level l of diagram j (its values: mb, multiplier lam[l]) */
+static void rev_bstep(const orc_state *S, int j, int l, const REAL *mb, const REAL *lam, double *gmb,
+                      double *glam, double alpha) {
+  const bdd_t *B = &S->bdd[j];
+  long long nb = S->ncanon[j], c = S->canon[j];
+  for (int u = B->first[l]; u < B->first[l + 1]; ++u) {
+    double g = gmb[nb + u];
+    gmb[nb + u] = 0.0;
+    if (g == 0.0) continue;
+    REAL x0 = child_val(mb + nb, B, l, B->lo[u]), x1 = child_val(mb + nb, B, l, B->hi[u]) + lam[c + l];
+    REAL s = mb[nb + u];
+    double w0 = sweight(x0, s, alpha), w1 = sweight(x1, s, alpha);
+    if (B->lo[u] >= 0) gmb[nb + B->first[l + 1] + B->lo[u]] += g * w0;
+    if (B->hi[u] >= 0) gmb[nb + B->first[l + 1] + B->hi[u]] += g * w1;
+    glam[c + l] += g * w1;
+  }
+}
+
+/* undo the marginals of level l: adjoints gm0, gm1 of m0, m1 go to mf (level l), mb (level l+1)
+ * and the multiplier lam[l] */
+static void rev_marginals(const orc_state *S, int j, int l, const rev_t *R, double gm0, double gm1) {
+  const bdd_t *B = &S->bdd[j];
+  long long nb = S->ncanon[j], c = S->canon[j];
+  REAL m0, m1;
+  level_marginals_s(B, R->lam0 + c, R->mf + nb, R->mb + nb, l, &m0, &m1, R->alpha);
+  for (int u = B->first[l]; u < B->first[l + 1]; ++u) {
+    int ch[2] = {B->lo[u], B->hi[u]};
+    for (int beta = 0; beta < 2; ++beta) {
+      double g = beta ? gm1 : gm0;
+      if (g == 0.0) continue;
+      REAL arc = (R->mf[nb + u] + (beta ? R->lam0[c + l] : (REAL)0)) + child_val(R->mb + nb, B, l, ch[beta]);
+      double w = sweight(arc, beta ? m1 : m0, R->alpha);
+      R->gmf[nb + u] += g * w;
+      if (ch[beta] >= 0) R->gmb[nb + B->first[l + 1] + ch[beta]] += g * w;
+      if (beta) R->glam[c + l] += g * w;
+    }
+  }
+}
+
+/* undo the forward step that produced level l (l >= 1) from level l-1 with multiplier lam[l-1] */
+static void rev_fstep(const orc_state *S, int j, int l, const REAL *mf, const REAL *lam, double *gmf,
+                      double *glam, double alpha) {
+  const bdd_t *B = &S->bdd[j];
+  long long nb = S->ncanon[j], c = S->canon[j];
+  for (int u = B->first[l - 1]; u < B->first[l]; ++u) {
+    int ch[2] = {B->lo[u], B->hi[u]};
+    for (int beta = 0; beta < 2; ++beta) {
+      if (ch[beta] < 0) continue;
+      int v = B->first[l] + ch[beta];
+      double g = gmf[nb + v];
+      if (g == 0.0) continue;
+      REAL arg = mf[nb + u] + (beta ? lam[c + l - 1] : (REAL)0);
+      double w = sweight(arg, mf[nb + v], alpha);
+      gmf[nb + u] += g * w;
+      if (beta) glam[c + l - 1] += g * w;
+    }
+  }
+  for (int v = B->first[l]; v < B->first[l + 1]; ++v) gmf[nb + v] = 0.0;
+}
+
+/* undo the update of variable i: glam holds the adjoints of the updated multipliers; on return
+ * it holds those of the multipliers before the update, and gd the adjoints of the differences */
+static void rev_update(const orc_state *S, int i, const REAL *d, const double *glam1, double *gd) {
+  int a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+  int nF = 0, neg = 0;
+  double gsum = 0.0, gforced = 0.0;
+  for (int q = 0; q < cnt; ++q) {
+    if (isinf(d[q])) { ++nF; gforced += glam1[q]; if (d[q] < 0) neg = 1; }
+    gsum += glam1[q];
+  }
+  for (int q = 0; q < cnt; ++q) {
+    if (nF == 0) gd[q] = -glam1[q] + gsum / cnt;
+    else if (!isinf(d[q]) && (neg ? d[q] > 0 : d[q] < 0)) gd[q] = -glam1[q] + gforced / nF;
+    else gd[q] = 0.0;
+  }
+}
+
+/*
+ * Gradient of LB_alpha after T smoothed iterations (started by orc_smooth_init) with respect to
+ * the costs: grad[n]; *lb_out = LB_alpha(T). Leaves the state after the T iterations.
+ */
+int orc_smooth_grad(orc_state *S, double alpha, int T, double *grad, double *lb_out) {
+  int rc = orc_smooth_init(S, alpha);
+  if (rc) return rc;
+  long long I = S->n_inc, N = S->n_nodes;
+  size_t nI = (size_t)(I ? I : 1), nN = (size_t)(N ? N : 1);
+  REAL *ck = (REAL *)malloc(nI * (size_t)(T + 1) * sizeof(REAL));
+  REAL *lam_mid = (REAL *)malloc(nI * sizeof(REAL)), *lam_end = (REAL *)malloc(nI * sizeof(REAL));
+  REAL *mf = (REAL *)malloc(nN * sizeof(REAL)), *mbT = (REAL *)malloc(nN * sizeof(REAL));
+  REAL *mbE = (REAL *)malloc(nN * sizeof(REAL));
+  double *gmf = (double *)calloc(nN, sizeof(double)), *gmb = (double *)calloc(nN, sizeof(double));
+  double *glam = (double *)calloc(nI, sizeof(double));
+  double *gl1 = (double *)malloc((size_t)(S->maxJ ? S->maxJ : 1) * sizeof(double));
+  double *gd = (double *)malloc((size_t)(S->maxJ ? S->maxJ : 1) * sizeof(double));
+  REAL *dv = (REAL *)malloc((size_t)(S->maxJ ? S->maxJ : 1) * sizeof(REAL));
+  if (!ck || !lam_mid || !lam_end || !mf || !mbT || !mbE || !gmf || !gmb || !glam || !gl1 || !gd || !dv) {
+    rc = ORC_NOMEM;
+    goto out;
+  }
+  get_lam(S, ck);
+  for (int t = 0; t < T; ++t) {
+    if ((rc = smooth_round(S, alpha))) goto out;
+    get_lam(S, ck + nI * (size_t)(t + 1));
+  }
+  S->lb = lower_bound_s(S, alpha);
+  if (lb_out) *lb_out = S->lb;
+  /* seed: d LB / d (root backward message) = 1 for every diagram */
+  for (int j = 0; j < S->m; ++j)
+    if (S->bdd[j].k) gmb[S->ncanon[j] + S->bdd[j].first[0]] = 1.0;
+  for (int t = T - 1; t >= 0; --t) {
+    /* recompute iteration t from its checkpoint */
+    double *lt = (double *)malloc(nI * sizeof(double));
+    for (size_t q = 0; q < (size_t)I; ++q) lt[q] = (double)ck[nI * (size_t)t + q];
+    set_lam(S, lt);
+    free(lt);
+    sweep_s(S, alpha);
+    get_msgs(S, mbT, 1);
+    for (int r = 0; r < S->n; ++r)
+      if ((rc = process_variable_s(S, S->order[r], 1, alpha))) goto out;
+    get_lam(S, lam_mid);
+    get_msgs(S, mf, 0);
+    for (int r = S->n - 1; r >= 0; --r)
+      if ((rc = process_variable_s(S, S->order[r], 0, alpha))) goto out;
+    get_lam(S, lam_end);
+    get_msgs(S, mbE, 1);
+    /* undo the backward pass: variables in forward order */
+    rev_t RB = {alpha, mf, mbE, lam_mid, lam_end, gmf, gmb, glam};
+    for (int r = 0; r < S->n; ++r) {
+      int i = S->order[r], a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+      if (!cnt) continue;
+      for (int q = 0; q < cnt; ++q)
+        rev_bstep(S, S->inc_bdd[a0 + q], S->inc_lvl[a0 + q], mbE, lam_end, gmb, glam, alpha);
+      for (int q = 0; q < cnt; ++q) {
+        int j = S->inc_bdd[a0 + q], l = S->inc_lvl[a0 + q];
+        long long nb = S->ncanon[j], c = S->canon[j];
+        REAL m0, m1;
+        level_marginals_s(&S->bdd[j], lam_mid + c, mf + nb, mbE + nb, l, &m0, &m1, alpha);
+        dv[q] = m1 - m0;
+        gl1[q] = glam[c + l];
+      }
+      rev_update(S, i, dv, gl1, gd);
+      for (int q = 0; q < cnt; ++q)
+        if (!isinf(dv[q])) rev_marginals(S, S->inc_bdd[a0 + q], S->inc_lvl[a0 + q], &RB, -gd[q], gd[q]);
+    }
+    /* undo the forward pass: variables in backward order */
+    rev_t RF = {alpha, mf, mbT, ck + nI * (size_t)t, lam_mid, gmf, gmb, glam};
+    for (int r = S->n - 1; r >= 0; --r) {
+      int i = S->order[r], a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+      if (!cnt) continue;
+      for (int q = 0; q < cnt; ++q) {
+        int j = S->inc_bdd[a0 + q], l = S->inc_lvl[a0 + q];
+        long long nb = S->ncanon[j], c = S->canon[j];
+        REAL m0, m1;
+        level_marginals_s(&S->bdd[j], RF.lam0 + c, mf + nb, mbT + nb, l, &m0, &m1, alpha);
+        dv[q] = m1 - m0;
+        gl1[q] = glam[c + l];
+      }
+      rev_update(S, i, dv, gl1, gd);
+      for (int q = 0; q < cnt; ++q) {
+        int j = S->inc_bdd[a0 + q], l = S->inc_lvl[a0 + q];
+        if (!isinf(dv[q])) rev_marginals(S, j, l, &RF, -gd[q], gd[q]);
+        if (l > 0) rev_fstep(S, j, l, mf, lam_mid, gmf, glam, alpha);
+        else gmf[S->ncanon[j] + S->bdd[j].first[0]] = 0.0;
+      }
+    }
+  }
+  /* undo the initial backward sweep (multipliers c / |J_i|), root level first */
+  {
+    double *l0 = (double *)malloc(nI * sizeof(double));
+    for (size_t q = 0; q < (size_t)I; ++q) l0[q] = (double)ck[q];
+    set_lam(S, l0);
+    free(l0);
+    sweep_s(S, alpha);
+    get_msgs(S, mbT, 1);
+    for (int j = 0; j < S->m; ++j)
+      for (int l = 0; l < S->bdd[j].k; ++l) rev_bstep(S, j, l, mbT, ck, gmb, glam, alpha);
+  }
+  for (int i = 0; i < S->n; ++i) {
+    int a0 = S->inc_ptr[i], cnt = S->inc_ptr[i + 1] - a0;
+    if (!cnt) {
+      REAL s = smin((REAL)0, (REAL)S->cost[i], alpha);
+      grad[i] = sweight((REAL)S->cost[i], s, alpha);
+      continue;
+    }
+    double g = 0.0;
+    for (int q = 0; q < cnt; ++q) g += glam[S->canon[S->inc_bdd[a0 + q]] + S->inc_lvl[a0 + q]];
+    grad[i] = g / cnt;
+  }
+  /* leave the state after the T iterations */
+  {
+    double *le = (double *)malloc(nI * sizeof(double));
+    for (size_t q = 0; q < (size_t)I; ++q) le[q] = (double)ck[nI * (size_t)T + q];
+    set_lam(S, le);
+    free(le);
+    sweep_s(S, alpha);
+  }
+out:
+  free(ck); free(lam_mid); free(lam_end); free(mf); free(mbT); free(mbE);
+  free(gmf); free(gmb); free(glam); free(gl1); free(gd); free(dv);
+  return rc;
+}

@@ -50,6 +50,15 @@ def _lib(prec: str):
     L.orc_checks.argtypes = [P, P]
     L.orc_count_solutions.argtypes = [P, P]
     L.orc_error.restype = C.c_char_p
+    L.orc_smooth_init.argtypes = [P, D]
+    L.orc_smooth_init.restype = I
+    L.orc_smooth_iterate.argtypes = [P, D, I, P]
+    L.orc_smooth_iterate.restype = I
+    L.orc_smooth_marginals.argtypes = [P, D, P, P]
+    L.orc_smooth_marginals.restype = I
+    L.orc_row_energies.argtypes = [P, D, P, P]
+    L.orc_smooth_grad.argtypes = [P, D, I, P, P]
+    L.orc_smooth_grad.restype = I
     L.orc_build_row.argtypes = [I, P, I, LL, LL, P, P, P, LL]
     L.orc_build_row.restype = LL
     _LIBS[prec] = L
@@ -140,6 +149,36 @@ class Oracle:
         nv = C.c_longlong()
         _check(self.L, self.L.orc_round(self.h, _p(M), _p(x), C.byref(obj), C.byref(nv)))
         return M, x, obj.value, nv.value
+
+    # smoothed variant (App. "Smoothing")
+    def smooth_init(self, alpha: float) -> float:
+        _check(self.L, self.L.orc_smooth_init(self.h, float(alpha)))
+        return self.lower_bound()
+
+    def smooth_iterate(self, alpha: float, iters: int) -> np.ndarray:
+        tr = np.zeros(max(iters, 1), np.float64)
+        _check(self.L, self.L.orc_smooth_iterate(self.h, float(alpha), int(iters), _p(tr)))
+        return tr[:iters]
+
+    def smooth_marginals(self, alpha: float):
+        m0 = np.zeros(self.n_incidences, np.float64)
+        m1 = np.zeros(self.n_incidences, np.float64)
+        _check(self.L, self.L.orc_smooth_marginals(self.h, float(alpha), _p(m0), _p(m1)))
+        return m0, m1
+
+    def row_energies(self, alpha: float):
+        """(E^j, E^j_alpha) per row at the current multipliers, from scratch."""
+        e = np.zeros(max(self.m, 1), np.float64)
+        ea = np.zeros(max(self.m, 1), np.float64)
+        self.L.orc_row_energies(self.h, float(alpha), _p(e), _p(ea))
+        return e[:self.m], ea[:self.m]
+
+    def smooth_grad(self, alpha: float, iters: int):
+        """(d LB_alpha(T) / d c, LB_alpha(T)) after T smoothed iterations from the initialisation."""
+        g = np.zeros(max(self.n, 1), np.float64)
+        lb = C.c_double()
+        _check(self.L, self.L.orc_smooth_grad(self.h, float(alpha), int(iters), _p(g), C.byref(lb)))
+        return g[:self.n], lb.value
 
     def count_solutions(self) -> np.ndarray:
         out = np.zeros(self.m, np.float64)

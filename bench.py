@@ -43,6 +43,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = ["paper_2009_00481_amd/csrc/kernels.hip", "paper_2009_00481_amd/csrc/kernels.h",
+                  "paper_2009_00481_amd/csrc/device.h",
                   "paper_2009_00481_amd/csrc/plan.cpp", "paper_2009_00481_amd/csrc/internal.h"]
 
 

@@ -241,6 +241,40 @@ int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
 int32_t bddmp_solver_round_primal(bddmp_solver *s, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated);
 
 /*
+ * Smoothed variant (App. "Smoothing"): every min of the forward steps, backward steps and
+ * min-marginals becomes the soft minimum smin(a, b) = -alpha log(exp(-a/alpha) + exp(-b/alpha))
+ * (eq. "marginal-log-sum-exp", the marginal log-sum-exp algebra of Table "algebras" in the log
+ * domain), with the update of eq. "mma-update" on those values; the bound is the smoothed dual
+ * LB_alpha = sum_j E^j_alpha (eq. "bdd-enery-smoothed") plus smin(0, c_i) for each variable in no
+ * row, with E^j >= E^j_alpha >= E^j - alpha log |X_j| (Prop. "Approximation guarantees"). Rows
+ * forcing a variable: only the rows whose move raises the smoothed bound hand their difference to
+ * the forced rows (d > 0 when a row forces x_i = 1, d < 0 when one forces x_i = 0). Messages and
+ * multipliers in fp32, bounds in fp64. Plans with a variable in more than 256 rows: INVALID_ARG.
+ *
+ * bddmp_smooth_workspace_bytes: device bytes of the workspace for n_iters iterations (multiplier
+ * checkpoints after each iteration and the adjoint arrays).
+ * bddmp_solver_smooth_run: from lambda = c / |J_i|, the smoothed initial sweep and n_iters smoothed
+ * iterations, each LB_alpha appended to the bound history, the multipliers after each iteration
+ * kept in ws (device, 256-byte aligned, >= the workspace bytes). Asynchronous.
+ * bddmp_solver_smooth_grad: dlb * d LB_alpha(n_iters) / d c into grad_dev (device float [n_vars],
+ * variable order), by reverse accumulation over the checkpoints a smooth_run with the same alpha,
+ * n_iters and ws left: each iteration is recomputed from its checkpoint, then its backward and
+ * forward passes are undone wave by wave in reverse order through the soft-minimum weights. The
+ * solver ends at the multipliers after n_iters iterations. Asynchronous.
+ */
+int32_t bddmp_smooth_workspace_bytes(const bddmp_plan *plan, int32_t n_iters, size_t *bytes);
+int32_t bddmp_solver_smooth_run(bddmp_solver *s, float alpha, int32_t n_iters, void *ws, size_t ws_bytes);
+int32_t bddmp_solver_smooth_grad(bddmp_solver *s, float alpha, int32_t n_iters, void *ws, size_t ws_bytes,
+                                 double dlb, float *grad_dev);
+
+/*
+ * Replaces the costs c (device double [n_vars]) used by bddmp_solver_reset and the smoothed run
+ * (lambda = c / |J_i| and the terms of variables in no row). The plan keeps its own costs: after
+ * this call bddmp_solver_instance_bounds returns BAD_STATE. Asynchronous.
+ */
+int32_t bddmp_solver_set_costs(bddmp_solver *s, const double *cost_dev);
+
+/*
  * Launch mode of bddmp_solver_iterate. enable = 1 (default): one iteration (every wave launch of
  * both passes and the bound reduction) is captured once as a HIP graph on a private stream and
  * replayed on the solver's stream, one graph launch per iteration; the bound's history slot comes

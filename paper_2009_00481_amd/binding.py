@@ -81,6 +81,10 @@ SIGNATURES = {
     "bddmp_solver_get_lambda": (_I32, [_P, _P]),
     "bddmp_solver_set_lambda": (_I32, [_P, _P]),
     "bddmp_solver_round_primal": (_I32, [_P, _P, _P, C.POINTER(_D), C.POINTER(_I64)]),
+    "bddmp_smooth_workspace_bytes": (_I32, [_P, _I32, C.POINTER(C.c_size_t)]),
+    "bddmp_solver_smooth_run": (_I32, [_P, C.c_float, _I32, _P, C.c_size_t]),
+    "bddmp_solver_smooth_grad": (_I32, [_P, C.c_float, _I32, _P, C.c_size_t, _D, _P]),
+    "bddmp_solver_set_costs": (_I32, [_P, _P]),
     "bddmp_solver_set_graphs": (_I32, [_P, _I32]),
     "bddmp_solver_set_groups": (_I32, [_P, _P]),
     "bddmp_solver_get_groups": (_I32, [_P, _P]),
@@ -271,6 +275,25 @@ def bddmp_solver_round_primal(h, M, n: int):
     nv = C.c_int64()
     _check(lib().bddmp_solver_round_primal(h, _dptr(M), _ptr(x), C.byref(obj), C.byref(nv)))
     return x[:n], obj.value, nv.value
+
+
+def bddmp_smooth_workspace_bytes(plan, n_iters: int) -> int:
+    b = C.c_size_t()
+    _check(lib().bddmp_smooth_workspace_bytes(plan, int(n_iters), C.byref(b)))
+    return int(b.value)
+
+
+def bddmp_solver_smooth_run(h, alpha: float, n_iters: int, ws, ws_bytes: int):
+    _check(lib().bddmp_solver_smooth_run(h, float(alpha), int(n_iters), _dptr(ws), C.c_size_t(int(ws_bytes))))
+
+
+def bddmp_solver_smooth_grad(h, alpha: float, n_iters: int, ws, ws_bytes: int, dlb: float, grad):
+    _check(lib().bddmp_solver_smooth_grad(h, float(alpha), int(n_iters), _dptr(ws), C.c_size_t(int(ws_bytes)),
+                                          float(dlb), _dptr(grad)))
+
+
+def bddmp_solver_set_costs(h, cost):
+    _check(lib().bddmp_solver_set_costs(h, _dptr(cost)))
 
 
 def bddmp_solver_set_graphs(h, enable: bool):

@@ -313,6 +313,27 @@ int32_t bddmp_solver_round_primal(bddmp_solver *h, float *M_dev, int8_t *x_host,
   return guarded([&] { return bddmp::solver_round_primal(*h->s, M_dev, x_host, obj, n_violated); });
 }
 
+int32_t bddmp_smooth_workspace_bytes(const bddmp_plan *h, int32_t n_iters, size_t *bytes) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  return bddmp::solver_smooth_workspace(h->plan, n_iters, bytes);
+}
+
+int32_t bddmp_solver_smooth_run(bddmp_solver *h, float alpha, int32_t n_iters, void *ws, size_t ws_bytes) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_smooth_run(*h->s, alpha, n_iters, ws, ws_bytes); });
+}
+
+int32_t bddmp_solver_smooth_grad(bddmp_solver *h, float alpha, int32_t n_iters, void *ws, size_t ws_bytes,
+                                 double dlb, float *grad_dev) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_smooth_grad(*h->s, alpha, n_iters, ws, ws_bytes, dlb, grad_dev); });
+}
+
+int32_t bddmp_solver_set_costs(bddmp_solver *h, const double *cost_dev) {
+  SOLVER_OR_FAIL(h);
+  return bddmp::solver_set_costs(*h->s, cost_dev);
+}
+
 int32_t bddmp_solver_set_graphs(bddmp_solver *h, int32_t enable) {
   SOLVER_OR_FAIL(h);
   return bddmp::solver_set_graphs(*h->s, enable);

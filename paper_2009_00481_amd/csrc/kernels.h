@@ -43,6 +43,7 @@ struct Dev {
   int32_t n_bwd_tiles;  // bound partials of big backward tiles start here
   const int32_t *inst_row;  // [n_inst + 1] first row of each instance
   double *inst_lb;          // [n_inst] per-instance bounds
+  double *lbc;              // [2] bound constants of the variables in no row: min-plus, smoothed
   long long *hist_n;        // bounds recorded so far (device counter; slot = count % hist_cap)
   int32_t hist_cap;
   uint32_t gsel;            // per tile width class, 4 bits: log2 of the lanes per general layer
@@ -63,12 +64,30 @@ hipError_t launch_lambda_out(const Dev &D, float *out, int I, hipStream_t s);
 hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s);
 // Bound of the backward sweep just run into the history ring at the device counter's slot, then
 // the counter advances (no host-side argument changes between iterations, so graphs can replay it).
-hipError_t launch_lb(const Dev &D, int nparts, double lb_const, hipStream_t s);
+// which: 0 adds the min-plus constant D.lbc[0], 1 the smoothed one D.lbc[1].
+hipError_t launch_lb(const Dev &D, int nparts, int which, hipStream_t s);
 hipError_t launch_set_counter(const Dev &D, long long value, hipStream_t s);
 // Per-instance bound of the last backward sweep (sum over the instance's rows of E^j, recomputed
 // from the messages and multipliers; instance k's constant term is added by the host).
 hipError_t launch_instance_bounds(const Dev &D, int n_inst, hipStream_t s);
 hipError_t launch_residual(const Dev &D, int n, hipStream_t s);
 hipError_t launch_round(const Dev &D, int n, int m, hipStream_t s);
+
+// Smoothed variant (smooth.hip).
+struct SmoothArgs {
+  float alpha;
+  float root_seed;        // adjoint of each root's new backward message in this pass
+  const float *lam_prev;  // multipliers before the pass's updates
+  const float *lam_upd;   // multipliers after the forward pass's updates
+  const float *mbt;       // backward messages the forward pass read
+  float *glam, *gmf, *gmb;
+};
+// One wave of a smoothed pass (adjoint = false) or of its adjoint (true).
+hipError_t launch_smooth_wave(int dir, int mode, bool adjoint, bool list, int nt, int tile0, const Dev &D,
+                              const SmoothArgs &A, hipStream_t s);
+// D.lbc[0] = sum of min(0, c_i), D.lbc[1] = sum of smin_alpha(0, c_i) over variables in no row.
+hipError_t launch_free_const(const Dev &D, int n, float alpha, hipStream_t s);
+hipError_t launch_smooth_grad(const Dev &D, const SmoothArgs &A, int n, float scale, float *grad, hipStream_t s);
+hipError_t launch_cost_in(const Dev &D, const double *c, int n, hipStream_t s);
 
 }  // namespace bddmp

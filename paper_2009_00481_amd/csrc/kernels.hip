@@ -17,39 +17,17 @@
 #include <cmath>
 #include <type_traits>
 
+#include "device.h"
 #include "kernels.h"
 
 namespace bddmp {
 
 namespace {
 
-// backward message behind a 2-bit child code of a narrow layer
-__device__ __forceinline__ float c2val(uint32_t code, float2 b) {
-  // codes 0, 1: node of the next level; 2 (kC2Bot): +inf; 3 (kC2Top): 0. Selects, no branches.
-  const float node = (code & 1u) ? b.y : b.x;
-  const float term = (code & 1u) ? 0.0f : INFINITY;
-  return (code & 2u) ? term : node;
-}
-
-// backward message behind a 16-bit child code of a general layer
-__device__ __forceinline__ float c16val(const float *__restrict__ mb, int cs, uint32_t c) {
-  return c < kTop ? mb[cs + int(c)] : (c == kTop ? 0.0f : INFINITY);
-}
-
 // multiplier update of eq. "mma-update"; rows forcing the variable (infinite difference) absorb
 // the finite differences of the others
 __device__ __forceinline__ float updated(float lam0, float d, float share, int nf) {
   return nf == 0 ? (lam0 - d) + share : (isinf(d) ? lam0 + share : lam0 - d);
-}
-
-// General record of a layer: own slot, child slot, own width, child width, base of the child
-// level's in-arc offsets (-1 without child level).
-struct GRec {
-  int os, cs, w, wc, rb;
-};
-__device__ __forceinline__ GRec grec_of(const Dev &D, int L) {
-  const int4 g = D.grec[L];
-  return {g.x, g.y, g.z & 0xFFFF, int(uint32_t(g.z) >> 16), g.w};
 }
 
 // One layer's work split around the J_i sum: begin() computes the min-marginals, push() /
@@ -256,30 +234,6 @@ constexpr int kFlatR = kFlatCap / kTile;   // nodes per lane
 
 __device__ __forceinline__ float staged(const float *cb, int c0, uint32_t c) {
   return c < kTop ? cb[c0 + int(c)] : (c == kTop ? 0.0f : INFINITY);
-}
-
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8, each XCD
-// with its own L2). Remap so that XCD x takes one contiguous run of the launch's tiles: lines at a
-// boundary between neighbouring tiles are then shared inside one L2 instead of across XCDs.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-  const int q = n / kXcds, r = n % kXcds;
-  const int x = b % kXcds, k = b / kXcds;
-  return x * q + min(x, r) + k;
-}
-
-// Sum of one double per lane over the workgroup in a fixed shape (butterfly inside each
-// wavefront, then the wavefront totals in order), so the result does not depend on timing.
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = int(threadIdx.x) >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  const int nw = int(blockDim.x) >> 6;
-  for (int q = 0; q < nw; ++q) s += sh[q];
-  __syncthreads();
-  return s;
 }
 
 // LIST: backward positions go through bwd_list (a wave that is not one contiguous layer range).
@@ -650,12 +604,12 @@ __global__ __launch_bounds__(256) void lb_stage_kernel(const Dev D, int nparts) 
   if (threadIdx.x == 0) D.part[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, double lb_const) {
+__global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, int which) {
   __shared__ double sh[kLbStage / 64];
   const double s = block_sum(D.part[threadIdx.x], sh);
   if (threadIdx.x == 0) {
     const long long n = *D.hist_n;
-    D.lb_hist[n % D.hist_cap] = s + lb_const;
+    D.lb_hist[n % D.hist_cap] = s + D.lbc[which];
     *D.hist_n = n + 1;
   }
 }
@@ -879,11 +833,11 @@ hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_lb(const Dev &D, int nparts, double lb_const, hipStream_t s) {
+hipError_t launch_lb(const Dev &D, int nparts, int which, hipStream_t s) {
   hipLaunchKernelGGL(lb_stage_kernel, dim3(kLbStage), dim3(256), 0, s, D, nparts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, s, D, lb_const);
+  hipLaunchKernelGGL(lb_final_kernel, dim3(1), dim3(kLbStage), 0, s, D, which);
   return hipGetLastError();
 }
 

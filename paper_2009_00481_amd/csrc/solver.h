@@ -26,6 +26,10 @@ int32_t solver_set_groups(Solver &S, const int32_t *lanes);
 int32_t solver_get_groups(const Solver &S, int32_t *lanes);
 int32_t solver_autotune(Solver &S, int32_t iters, int32_t *lanes);
 int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out);
+int32_t solver_smooth_workspace(const Plan &P, int32_t T, size_t *bytes);
+int32_t solver_smooth_run(Solver &S, float alpha, int32_t T, void *ws, size_t bytes);
+int32_t solver_smooth_grad(Solver &S, float alpha, int32_t T, void *ws, size_t bytes, double dlb, float *grad);
+int32_t solver_set_costs(Solver &S, const double *cost_dev);
 void solver_destroy(Solver *S);
 
 }  // namespace bddmp

@@ -31,6 +31,7 @@ struct Solver {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   uint32_t graph_gsel = 0;
+  bool costs_replaced = false;  // bddmp_solver_set_costs was called (instance constants are stale)
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -102,11 +103,11 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
 
 // the bound of the backward sweep just run, from its per-tile partials, into the history slot the
 // device counter names (the caller advances the host count S.n_hist)
-int32_t enqueue_lb(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
+int32_t enqueue_lb(Solver &S, std::vector<EventPair> *ev, hipStream_t st, int which = 0) {
   const Plan &P = *S.plan;
   Timer tm{ev};
   if (int32_t rc = tm.start(st, 2)) return rc;
-  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart), P.lb_const, st), "bound reduction")) return rc;
+  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart), which, st), "bound reduction")) return rc;
   return tm.stop(st, 1);
 }
 
@@ -210,6 +211,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.out0 = D.out1 = nullptr;
   D.n_bwd_tiles = int32_t(P.bwd_tiles.size() / 2);
   D.hist_n = reinterpret_cast<long long *>(b + A.scal + 64);
+  D.lbc = reinterpret_cast<double *>(b + A.scal + 80);
   D.hist_cap = P.hist_cap;
   D.inst_row = reinterpret_cast<const int32_t *>(b + A.inst_row);
   D.inst_lb = reinterpret_cast<double *>(b + A.inst_lb);
@@ -268,6 +270,7 @@ int32_t solver_reset(Solver &S) {
   if (int32_t rc = launched(launch_init_lambda(S.D, int(P.I), S.stream), "init_lambda")) return rc;
   if (int32_t rc = launched(launch_root_zero(S.D, P.m, S.stream), "root_zero")) return rc;
   if (int32_t rc = launched(launch_set_counter(S.D, S.n_hist, S.stream), "set_counter")) return rc;
+  if (int32_t rc = launched(launch_free_const(S.D, P.n, 1.0f, S.stream), "free_const")) return rc;
   S.iters = 0;
   return initial_sweep(S);
 }
@@ -315,6 +318,7 @@ int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_
 int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n) {
   const Plan &P = *S.plan;
   const int32_t n_inst = int32_t(P.inst_lb_const.size());
+  if (S.costs_replaced) return set_error(BDDMP_BAD_STATE, "instance bounds use the plan's costs; costs were replaced");
   if (!lb_host || n != n_inst)
     return set_error(BDDMP_INVALID_ARG, "lb array must hold n_instances = " + std::to_string(n_inst) + " values");
   if (int32_t rc = launched(launch_instance_bounds(S.D, n_inst, S.stream), "instance_bounds")) return rc;
@@ -479,6 +483,157 @@ int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
   r.fwd_bytes = pass_bytes * n;
   r.bwd_bytes = pass_bytes * n;
   *out = r;
+  return BDDMP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// smoothed variant and its derivative
+// ---------------------------------------------------------------------------------------------
+
+namespace {
+
+struct SmoothWs {
+  float *ckpt, *lam_mid, *mbt, *glam, *gmf, *gmb;
+  size_t total;
+};
+
+SmoothWs smooth_layout(const Plan &P, int32_t T, char *base) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t I = size_t(std::max<int64_t>(P.I, 1)), S = size_t(P.S + 4), Sc = size_t(P.Sc + 4);
+  SmoothWs w{};
+  size_t off = 0;
+  auto take = [&](size_t floats) {
+    float *p = reinterpret_cast<float *>(base + off);
+    off = al(off + 4 * floats);
+    return p;
+  };
+  w.ckpt = take(I * size_t(T + 1));
+  w.lam_mid = take(I);
+  w.mbt = take(Sc);
+  w.glam = take(I);
+  w.gmf = take(S);
+  w.gmb = take(Sc);
+  w.total = off;
+  return w;
+}
+
+int32_t smooth_pass(Solver &S, int dir, int mode, bool adjoint, const SmoothArgs &A) {
+  const Plan &P = *S.plan;
+  const auto &waves = dir == kFwd ? P.fwd_waves : P.bwd_waves;
+  const int nw = int(waves.size());
+  for (int q = 0; q < nw; ++q) {
+    const WaveRange &wr = waves[size_t(adjoint ? nw - 1 - q : q)];
+    const int nt = wr.tile_end - wr.tile_begin;
+    const bool list = dir == kBwd && wr.list;
+    if (int32_t rc = launched(launch_smooth_wave(dir, mode, adjoint, list, nt, wr.tile_begin, S.D, A, S.stream),
+                              adjoint ? "smoothed adjoint wave" : "smoothed wave"))
+      return rc;
+  }
+  return BDDMP_OK;
+}
+
+int32_t smooth_check(Solver &S, float alpha, int32_t T, void *ws, size_t bytes, SmoothWs &w) {
+  const Plan &P = *S.plan;
+  if (!(alpha > 0.0f) || !std::isfinite(alpha)) return set_error(BDDMP_INVALID_ARG, "alpha must be positive");
+  if (T < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
+  if (!P.fwd_big.empty() || !P.bwd_big.empty())
+    return set_error(BDDMP_INVALID_ARG, "the smoothed passes take variables in at most 256 rows");
+  w = smooth_layout(P, T, static_cast<char *>(ws));
+  if (!ws || bytes < w.total) return set_error(BDDMP_INVALID_ARG, "workspace too small: need " + std::to_string(w.total));
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(BDDMP_INVALID_ARG, "workspace not 256-byte aligned");
+  return BDDMP_OK;
+}
+
+hipError_t copy_f(float *dst, const float *src, int64_t n, hipStream_t s) {
+  return n > 0 ? hipMemcpyAsync(dst, src, 4 * size_t(n), hipMemcpyDeviceToDevice, s) : hipSuccess;
+}
+
+}  // namespace
+
+int32_t solver_smooth_workspace(const Plan &P, int32_t T, size_t *bytes) {
+  if (T < 0 || !bytes) return set_error(BDDMP_INVALID_ARG, "negative iteration count or null out");
+  *bytes = smooth_layout(P, T, nullptr).total;
+  return BDDMP_OK;
+}
+
+// Smoothed Alg. "Min-marginal averaging" from lambda = c / |J_i|: the smoothed initial sweep and T
+// smoothed iterations, each bound LB_alpha appended to the history; lambda after each iteration
+// kept in the workspace (checkpoint t = lambda after t iterations, in storage order).
+int32_t solver_smooth_run(Solver &S, float alpha, int32_t T, void *ws, size_t bytes) {
+  const Plan &P = *S.plan;
+  SmoothWs w{};
+  if (int32_t rc = smooth_check(S, alpha, T, ws, bytes, w)) return rc;
+  SmoothArgs A{alpha, 0.0f, nullptr, nullptr, nullptr, w.glam, w.gmf, w.gmb};
+  const int nslots = int(P.S + 4), ncslots = int(P.Sc + 4);
+  if (int32_t rc = launched(launch_fill(S.D.mf, INFINITY, nslots, S.stream), "fill")) return rc;
+  if (int32_t rc = launched(launch_fill(S.D.mbc, INFINITY, ncslots, S.stream), "fill")) return rc;
+  if (int32_t rc = launched(launch_init_lambda(S.D, int(P.I), S.stream), "init_lambda")) return rc;
+  if (int32_t rc = launched(launch_root_zero(S.D, P.m, S.stream), "root_zero")) return rc;
+  if (int32_t rc = launched(launch_free_const(S.D, P.n, alpha, S.stream), "free_const")) return rc;
+  if (int32_t rc = smooth_pass(S, kBwd, kNoUpdate, false, A)) return rc;
+  if (int32_t rc = enqueue_lb(S, nullptr, S.stream, 1)) return rc;
+  S.n_hist++;
+  S.iters = 0;
+  HIP_TRY(copy_f(w.ckpt, S.D.lam, P.I, S.stream), "hipMemcpyAsync");
+  for (int32_t t = 0; t < T; ++t) {
+    if (int32_t rc = smooth_pass(S, kFwd, kUpdate, false, A)) return rc;
+    if (int32_t rc = smooth_pass(S, kBwd, kUpdate, false, A)) return rc;
+    if (int32_t rc = enqueue_lb(S, nullptr, S.stream, 1)) return rc;
+    S.n_hist++;
+    S.iters++;
+    HIP_TRY(copy_f(w.ckpt + size_t(std::max<int64_t>(P.I, 1)) * size_t(t + 1), S.D.lam, P.I, S.stream), "hipMemcpyAsync");
+  }
+  return BDDMP_OK;
+}
+
+// d LB_alpha(T) / d c times dlb into grad (device float [n], variable order), by reverse
+// accumulation over the checkpoints of solver_smooth_run (same alpha, T and workspace). Each
+// iteration is recomputed from its checkpoint (the initial sweep of lambda_t gives the backward
+// messages it started from), then its backward and forward passes are undone wave by wave in
+// reverse order. Leaves the solver at lambda_T with its backward messages.
+int32_t solver_smooth_grad(Solver &S, float alpha, int32_t T, void *ws, size_t bytes, double dlb, float *grad) {
+  const Plan &P = *S.plan;
+  SmoothWs w{};
+  if (int32_t rc = smooth_check(S, alpha, T, ws, bytes, w)) return rc;
+  if (!grad && P.n > 0) return set_error(BDDMP_INVALID_ARG, "null gradient output");
+  const size_t I1 = size_t(std::max<int64_t>(P.I, 1));
+  const int nslots = int(P.S + 4), ncslots = int(P.Sc + 4);
+  if (int32_t rc = launched(launch_fill(w.glam, 0.0f, int(I1), S.stream), "fill")) return rc;
+  if (int32_t rc = launched(launch_fill(w.gmf, 0.0f, nslots, S.stream), "fill")) return rc;
+  if (int32_t rc = launched(launch_fill(w.gmb, 0.0f, ncslots, S.stream), "fill")) return rc;
+  SmoothArgs A{alpha, 0.0f, nullptr, nullptr, w.mbt, w.glam, w.gmf, w.gmb};
+  for (int32_t t = T - 1; t >= 0; --t) {
+    const float *ck = w.ckpt + I1 * size_t(t);
+    HIP_TRY(copy_f(S.D.lam, ck, P.I, S.stream), "hipMemcpyAsync");
+    if (int32_t rc = smooth_pass(S, kBwd, kNoUpdate, false, A)) return rc;
+    HIP_TRY(copy_f(w.mbt, S.D.mbc, ncslots, S.stream), "hipMemcpyAsync");
+    if (int32_t rc = smooth_pass(S, kFwd, kUpdate, false, A)) return rc;
+    HIP_TRY(copy_f(w.lam_mid, S.D.lam, P.I, S.stream), "hipMemcpyAsync");
+    if (int32_t rc = smooth_pass(S, kBwd, kUpdate, false, A)) return rc;
+    SmoothArgs AB = A;
+    AB.root_seed = t == T - 1 ? float(dlb) : 0.0f;
+    AB.lam_prev = w.lam_mid;
+    if (int32_t rc = smooth_pass(S, kBwd, kUpdate, true, AB)) return rc;
+    SmoothArgs AF = A;
+    AF.lam_prev = ck;
+    AF.lam_upd = w.lam_mid;
+    if (int32_t rc = smooth_pass(S, kFwd, kUpdate, true, AF)) return rc;
+  }
+  HIP_TRY(copy_f(S.D.lam, w.ckpt, P.I, S.stream), "hipMemcpyAsync");
+  if (int32_t rc = smooth_pass(S, kBwd, kNoUpdate, false, A)) return rc;
+  SmoothArgs A0 = A;
+  A0.root_seed = T == 0 ? float(dlb) : 0.0f;
+  if (int32_t rc = smooth_pass(S, kBwd, kNoUpdate, true, A0)) return rc;
+  if (int32_t rc = launched(launch_smooth_grad(S.D, A, P.n, float(dlb), grad, S.stream), "smooth_grad")) return rc;
+  HIP_TRY(copy_f(S.D.lam, w.ckpt + I1 * size_t(T), P.I, S.stream), "hipMemcpyAsync");
+  return smooth_pass(S, kBwd, kNoUpdate, false, A);
+}
+
+int32_t solver_set_costs(Solver &S, const double *cost_dev) {
+  const Plan &P = *S.plan;
+  if (!cost_dev && P.n > 0) return set_error(BDDMP_INVALID_ARG, "null costs");
+  if (int32_t rc = launched(launch_cost_in(S.D, cost_dev, P.n, S.stream), "cost_in")) return rc;
+  S.costs_replaced = true;
   return BDDMP_OK;
 }
 

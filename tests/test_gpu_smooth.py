@@ -1,0 +1,207 @@
+"""GPU tests of the smoothed variant and its hand-written adjoint (App. "Smoothing").
+
+Forward: the smoothed bound trace and multipliers against the fp64 oracle at the same bar as the
+min-plus path (relative 1e-4). Gradient: against the oracle's fp64 reverse accumulation over
+every coordinate, against fp64 central finite differences of the oracle's bound on sampled
+coordinates of the 16x16 Potts stand-in, and at T = 0 against the argmin indicator as alpha -> 0.
+Gradient tolerance, relative to max(1, max |g|): the GPU differentiates its own fp32 trajectory,
+which departs from the fp64 one by rounding; the soft-minimum weights move by (departure)/alpha,
+so the bar scales with 1/alpha: 2e-4 / alpha, capped at 2e-2.
+"""
+import numpy as np
+import pytest
+
+from parity import REL, assert_incidence_close, assert_trace_close, incidence_scale
+from oracle import Oracle
+from paper_2009_00481_amd import binding as B
+from paper_2009_00481_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _grad_tol(alpha):
+    return min(2e-4 / alpha, 2e-2)
+
+
+def _case(name):
+    if name == "cfg1":
+        return I.config(1)
+    if name == "5sub":
+        return I.config("5sub")
+    if name == "tomo":
+        return I.tomography(6, seed=1, unary="normal")
+    if name == "rand":
+        return I.random_ilp(40, 30, kmax=8, cmax=3, seed=2)
+    if name == "forced":
+        return I.from_rows(8, [0.3, -0.7, 0.2, 0.9, -0.4, 0.25, 0.5, -0.1],
+                           [([0, 1], [2, 3], 0, 5), ([2, 3], [1, 1], 1, 0), ([0, 2, 4], [1, 1, 1], 1, 2),
+                            ([1, 3, 5], [1, -1, 1], 2, 1), ([4, 5], [1, 1], 0, 1), ([4, 6, 7], [1, 1, 1], 0, 1)],
+                           order=[3, 1, 5, 0, 2, 4, 7, 6])
+    raise ValueError(name)
+
+
+def _gpu_smooth(ilp, alpha, T, grad=True):
+    import torch
+
+    plan = B.Plan(B.Problem.from_ilp(ilp), hist_cap=max(64, T + 4))
+    s = B.Solver(plan)
+    nb = B.bddmp_smooth_workspace_bytes(plan.h, T)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+    B.bddmp_solver_smooth_run(s.h, alpha, T, ws, nb)
+    hist = s.lb_history(T + 1)
+    lam = s.get_lambda().cpu().numpy().astype(np.float64)
+    g = None
+    if grad:
+        gt = torch.empty(max(ilp.n, 1), dtype=torch.float32, device="cuda")
+        B.bddmp_solver_smooth_grad(s.h, alpha, T, ws, nb, 1.0, gt)
+        g = gt[:ilp.n].cpu().numpy().astype(np.float64)
+        lam_after = s.get_lambda().cpu().numpy().astype(np.float64)
+        torch.cuda.synchronize()
+        assert np.array_equal(lam_after, lam)  # the solver ends where the run ended
+    torch.cuda.synchronize()
+    return dict(hist=hist, lam=lam, grad=g, solver=s, plan=plan)
+
+
+CASES = ["cfg1", "5sub", "tomo", "rand", "forced"]
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.1, 0.01])
+@pytest.mark.parametrize("name", CASES)
+def test_smoothed_run_matches_oracle(name, alpha):
+    ilp = _case(name)
+    T = 20
+    print(f"[smooth] {name} alpha={alpha}", flush=True)
+    r = _gpu_smooth(ilp, alpha, T, grad=False)
+    o = Oracle(ilp)
+    lb0 = o.smooth_init(alpha)
+    tr = o.smooth_iterate(alpha, T)
+    assert_trace_close(r["hist"], np.concatenate([[lb0], tr]))
+    lam_ref = o.lam()
+    assert_incidence_close(r["lam"], lam_ref, incidence_scale(ilp, lam_ref), what="lambda")
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.1, 0.01])
+@pytest.mark.parametrize("T", [0, 3, 20])
+@pytest.mark.parametrize("name", CASES)
+def test_gradient_matches_oracle_adjoint(name, alpha, T):
+    ilp = _case(name)
+    print(f"[smooth-grad] {name} alpha={alpha} T={T}", flush=True)
+    r = _gpu_smooth(ilp, alpha, T)
+    g_ref, lb_ref = Oracle(ilp).smooth_grad(alpha, T)
+    assert r["hist"][-1] == pytest.approx(lb_ref, rel=REL, abs=REL)
+    err = np.abs(r["grad"] - g_ref).max() / max(1.0, np.abs(g_ref).max())
+    print(f"  max rel err {err:.3g} (tol {_grad_tol(alpha):.3g})", flush=True)
+    assert err <= _grad_tol(alpha)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.1, 0.01])
+def test_gradient_against_finite_differences_on_16x16(alpha):
+    """The differentiable workload's check: 50 iterations, fp64 central differences (h = 1e-6) of the
+    oracle's smoothed bound on sampled costs of the 16x16, 4-label Potts stand-in."""
+    ilp = I.config("5sub")
+    T = 50
+    r = _gpu_smooth(ilp, alpha, T)
+    idx = np.random.default_rng(1).choice(ilp.n, size=10, replace=False)
+    h = 1e-6
+    fd = []
+    for i in idx:
+        v = []
+        for sgn in (1, -1):
+            c = ilp.cost.copy()
+            c[i] += sgn * h
+            q = I.ILP(ilp.n, c, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, ilp.order)
+            o = Oracle(q)
+            o.smooth_init(alpha)
+            v.append(o.smooth_iterate(alpha, T)[-1])
+        fd.append((v[0] - v[1]) / (2 * h))
+    fd = np.array(fd)
+    err = np.abs(r["grad"][idx] - fd).max() / max(1.0, np.abs(fd).max())
+    print(f"[fd] alpha={alpha} max rel err {err:.3g}", flush=True)
+    assert err <= _grad_tol(alpha)
+
+
+def test_gradient_at_t0_tends_to_argmin_indicator():
+    rows = [([0, 1, 2], [1, 1, 1], 0, 1), ([1, 2, 3], [1, 1, 1], 1, 2), ([3, 4], [1, -1], 2, 0)]
+    ilp = I.from_rows(5, [0.9, -0.6, 0.2, -0.3, 0.5], rows)
+    r = _gpu_smooth(ilp, 1e-3, 0)
+    # argmin of each row at lambda = c / |J_i| (unique here), averaged over the variable's rows
+    import itertools
+
+    nj = np.zeros(ilp.n)
+    want = np.zeros(ilp.n)
+    for vs, cs, sense, rhs in rows:
+        lam = {v: ilp.cost[v] / sum(v in rr[0] for rr in rows) for v in vs}
+        best, bx = np.inf, None
+        for x in itertools.product([0, 1], repeat=len(vs)):
+            lhs = int(np.dot(cs, x))
+            ok = lhs == rhs if sense == 0 else (lhs <= rhs if sense == 1 else lhs >= rhs)
+            if ok and sum(lam[v] * xi for v, xi in zip(vs, x)) < best:
+                best, bx = sum(lam[v] * xi for v, xi in zip(vs, x)), x
+        for v, xi in zip(vs, bx):
+            want[v] += xi
+            nj[v] += 1
+    want /= nj
+    np.testing.assert_allclose(r["grad"], want, atol=1e-4)
+
+
+def test_runs_are_bitwise_repeatable():
+    ilp = I.config("5sub")
+    a = _gpu_smooth(ilp, 0.1, 10)
+    b = _gpu_smooth(ilp, 0.1, 10)
+    assert np.array_equal(a["hist"], b["hist"])
+    assert np.array_equal(a["grad"], b["grad"])
+
+
+def test_autograd_function():
+    import torch
+
+    from paper_2009_00481_amd.smooth import smoothed_bound
+
+    ilp = I.config("5sub")
+    alpha, T = 0.1, 8
+    s = B.Solver(B.Plan(B.Problem.from_ilp(ilp), hist_cap=64))
+    cost = torch.tensor(ilp.cost, dtype=torch.float64, device="cuda", requires_grad=True)
+    lb = smoothed_bound(cost, s, alpha, T)
+    lb.backward()
+    g_ref, lb_ref = Oracle(ilp).smooth_grad(alpha, T)
+    assert float(lb) == pytest.approx(lb_ref, rel=REL)
+    g = cost.grad.cpu().numpy()
+    assert np.abs(g - g_ref).max() / max(1.0, np.abs(g_ref).max()) <= _grad_tol(alpha)
+    # a scaled upstream gradient scales the result; a changed cost changes the bound as the oracle's
+    cost2 = (cost.detach() * 1.5).requires_grad_(True)
+    lb2 = smoothed_bound(cost2, s, alpha, T)
+    (3.0 * lb2).backward()
+    q = I.ILP(ilp.n, ilp.cost * 1.5, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, ilp.order)
+    g2_ref, lb2_ref = Oracle(q).smooth_grad(alpha, T)
+    assert float(lb2) == pytest.approx(lb2_ref, rel=REL)
+    assert np.abs(cost2.grad.cpu().numpy() - 3.0 * g2_ref).max() / max(1.0, 3 * np.abs(g2_ref).max()) <= _grad_tol(alpha)
+
+
+def test_smooth_argument_errors():
+    import torch
+
+    ilp = I.config(1)
+    plan = B.Plan(B.Problem.from_ilp(ilp))
+    s = B.Solver(plan)
+    nb = B.bddmp_smooth_workspace_bytes(plan.h, 5)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for bad_alpha in (0.0, -1.0):
+        with pytest.raises(B.BddmpError) as e:
+            B.bddmp_solver_smooth_run(s.h, bad_alpha, 5, ws, nb)
+        assert e.value.code == -1
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_smooth_run(s.h, 1.0, 6, ws, nb)
+    assert e.value.code == -1
+    rows = [([0, k], [1, 1], 1, 1) for k in range(1, 301)]
+    big = B.Plan(B.Problem.from_ilp(I.from_rows(301, np.ones(301), rows)))
+    sb = B.Solver(big)
+    nb2 = B.bddmp_smooth_workspace_bytes(big.h, 1)
+    ws2 = torch.empty(nb2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_smooth_run(sb.h, 1.0, 1, ws2, nb2)
+    assert e.value.code == -1
+    s.set_costs(torch.tensor(ilp.cost, dtype=torch.float64, device="cuda")) if hasattr(s, "set_costs") else \
+        B.bddmp_solver_set_costs(s.h, torch.tensor(ilp.cost, dtype=torch.float64, device="cuda"))
+    with pytest.raises(B.BddmpError) as e:
+        s.instance_bounds()
+    assert e.value.code == -7

@@ -11,6 +11,10 @@ relaxed and marginalised once per pass). The roofline object prices the dominant
 algorithmic bytes (20 per node and 8 per incidence per pass) against MI355X HBM peak; cpu_baseline
 is the fp64 CPU oracle on the same instance, one thread, on a bounded sample of iterations.
 
+smoothed_vs_plain: the differentiable form (smoothed iterations with checkpoints, then the adjoint
+giving d LB_alpha / d c) on Potts 128x128 with 4 labels, 50 iterations, alpha in {1, 0.1, 0.01},
+against plain min-plus iterations on the same instance.
+
 batched_vs_plain: the batched workload (256 tomography and tracking instances of uneven size) in
 one schedule against the same instances run one after another through their own plans; a sample of
 instances is compared bitwise.
@@ -140,6 +144,45 @@ def batched_vs_plain(args, B, I, torch):
             "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s}}
 
 
+def smoothed_vs_plain(args, B, I, torch):
+    """The differentiable form: smoothed DBCA forward (T iterations with per-iteration multiplier
+    checkpoints) and its adjoint (d LB_alpha / d c), against plain min-plus iterations on the same
+    instance (Potts 128x128, 4 labels)."""
+    ilp = I.config(5)
+    T = args.smooth_iters
+    plan = B.Plan(B.Problem.from_ilp(ilp), hist_cap=max(4096, T + 8))
+    st = plan.stats
+    s = B.Solver(plan)
+    nb = B.bddmp_smooth_workspace_bytes(plan.h, T)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+    grad = torch.empty(max(int(st.n_vars), 1), dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    plain_ms = timed(lambda: (B.bddmp_solver_reset(s.h), B.bddmp_solver_iterate(s.h, T))) / T
+    out = {"workload": "potts128x128_L4", "iterations": T, "n_nodes": int(st.n_nodes),
+           "n_incidences": int(st.n_incidences), "workspace_bytes": nb, "plain_ms_per_iter": plain_ms,
+           "alphas": {}}
+    for alpha in (1.0, 0.1, 0.01):
+        fwd = timed(lambda: B.bddmp_solver_smooth_run(s.h, alpha, T, ws, nb))
+        lb = float(s.lb_history(1)[-1])
+        bwd = timed(lambda: B.bddmp_solver_smooth_grad(s.h, alpha, T, ws, nb, 1.0, grad))
+        out["alphas"][str(alpha)] = {"forward_ms": fwd, "adjoint_ms": bwd, "forward_ms_per_iter": fwd / T,
+                                     "adjoint_over_forward": bwd / fwd, "smoothed_over_plain": fwd / T / plain_ms,
+                                     "lb_alpha": lb,
+                                     "grad_abs_sum": float(grad[:int(st.n_vars)].abs().sum())}
+    del s, ws, grad
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +194,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-smoothed", action="store_true", help="skip the smoothed-vs-plain comparison")
+    ap.add_argument("--smooth-iters", type=int, default=50)
+    ap.add_argument("--only", choices=["batched", "smoothed"], default=None,
+                    help="run only this comparison and print its object (profiling)")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--batch-plain-iters", type=int, default=3)
@@ -178,6 +225,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.only:
+        torch.cuda.set_device(0)
+        fn = batched_vs_plain if args.only == "batched" else smoothed_vs_plain
+        print(json.dumps({args.only: fn(args, B, I, torch)}), flush=True)
+        return
 
     cfg, T = WORKLOADS[args.workload]
     if args.iters:
@@ -281,6 +334,11 @@ def main():
                "s_per_iter": cpu_s / done}
         del o
 
+    smoothed = None
+    if not args.no_smoothed:
+        smoothed = smoothed_vs_plain(args, B, I, torch)
+        log(f"[bench] smoothed vs plain: {json.dumps(smoothed['alphas'])}")
+
     batched = None
     if not args.no_batched:
         del s
@@ -302,6 +360,7 @@ def main():
         "host_build_s": {"generate": gen_s, "plan": plan_s, "bind_upload": bind_s},
         "roofline": roofline, "cpu_baseline": cpu,
         "batched_vs_plain": batched,
+        "smoothed_vs_plain": smoothed,
     }
     print(json.dumps(rec), flush=True)
 

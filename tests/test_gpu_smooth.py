@@ -4,9 +4,11 @@ Forward: the smoothed bound trace and multipliers against the fp64 oracle at the
 min-plus path (relative 1e-4). Gradient: against the oracle's fp64 reverse accumulation over
 every coordinate, against fp64 central finite differences of the oracle's bound on sampled
 coordinates of the 16x16 Potts stand-in, and at T = 0 against the argmin indicator as alpha -> 0.
-Gradient tolerance, relative to max(1, max |g|): the GPU differentiates its own fp32 trajectory,
-which departs from the fp64 one by rounding; the soft-minimum weights move by (departure)/alpha,
-so the bar scales with 1/alpha: 2e-4 / alpha, capped at 2e-2.
+Gradient tolerance, relative to max(1, max |g|): the GPU differentiates its own fp32 trajectory
+with fp32 adjoints. Each of the 2 (T + 1) passes rounds a multiplier's adjoint in the sum over its
+|J_i| rows and in each of about 2 further steps (weight, product), each rounding at most 2^-24
+relative; with a conditioning margin of 16 the bar is 2^-24 * 64 * (T + 1) * max |J_i|, and never
+below 1e-4 (the forward bar).
 """
 import numpy as np
 import pytest
@@ -19,8 +21,8 @@ from paper_2009_00481_amd import instances as I
 pytestmark = pytest.mark.gpu
 
 
-def _grad_tol(alpha):
-    return min(2e-4 / alpha, 2e-2)
+def _grad_tol(T, max_j):
+    return max(1e-4, 2.0 ** -24 * 64 * (T + 1) * max_j)
 
 
 def _case(name):
@@ -90,8 +92,9 @@ def test_gradient_matches_oracle_adjoint(name, alpha, T):
     g_ref, lb_ref = Oracle(ilp).smooth_grad(alpha, T)
     assert r["hist"][-1] == pytest.approx(lb_ref, rel=REL, abs=REL)
     err = np.abs(r["grad"] - g_ref).max() / max(1.0, np.abs(g_ref).max())
-    print(f"  max rel err {err:.3g} (tol {_grad_tol(alpha):.3g})", flush=True)
-    assert err <= _grad_tol(alpha)
+    tol = _grad_tol(T, r["plan"].stats.max_rows_per_var)
+    print(f"  max rel err {err:.3g} (tol {tol:.3g})", flush=True)
+    assert err <= tol
 
 
 @pytest.mark.parametrize("alpha", [1.0, 0.1, 0.01])
@@ -117,7 +120,8 @@ def test_gradient_against_finite_differences_on_16x16(alpha):
     fd = np.array(fd)
     err = np.abs(r["grad"][idx] - fd).max() / max(1.0, np.abs(fd).max())
     print(f"[fd] alpha={alpha} max rel err {err:.3g}", flush=True)
-    assert err <= _grad_tol(alpha)
+    # plus the error of the differences themselves: truncation O(h^2) and rounding 1e-16 |LB| / h
+    assert err <= _grad_tol(T, r["plan"].stats.max_rows_per_var) + 1e-6
 
 
 def test_gradient_at_t0_tends_to_argmin_indicator():
@@ -166,7 +170,8 @@ def test_autograd_function():
     g_ref, lb_ref = Oracle(ilp).smooth_grad(alpha, T)
     assert float(lb) == pytest.approx(lb_ref, rel=REL)
     g = cost.grad.cpu().numpy()
-    assert np.abs(g - g_ref).max() / max(1.0, np.abs(g_ref).max()) <= _grad_tol(alpha)
+    tol = _grad_tol(T, s.plan.stats.max_rows_per_var)
+    assert np.abs(g - g_ref).max() / max(1.0, np.abs(g_ref).max()) <= tol
     # a scaled upstream gradient scales the result; a changed cost changes the bound as the oracle's
     cost2 = (cost.detach() * 1.5).requires_grad_(True)
     lb2 = smoothed_bound(cost2, s, alpha, T)
@@ -174,7 +179,7 @@ def test_autograd_function():
     q = I.ILP(ilp.n, ilp.cost * 1.5, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, ilp.order)
     g2_ref, lb2_ref = Oracle(q).smooth_grad(alpha, T)
     assert float(lb2) == pytest.approx(lb2_ref, rel=REL)
-    assert np.abs(cost2.grad.cpu().numpy() - 3.0 * g2_ref).max() / max(1.0, 3 * np.abs(g2_ref).max()) <= _grad_tol(alpha)
+    assert np.abs(cost2.grad.cpu().numpy() - 3.0 * g2_ref).max() / max(1.0, 3 * np.abs(g2_ref).max()) <= tol
 
 
 def test_smooth_argument_errors():
@@ -200,8 +205,7 @@ def test_smooth_argument_errors():
     with pytest.raises(B.BddmpError) as e:
         B.bddmp_solver_smooth_run(sb.h, 1.0, 1, ws2, nb2)
     assert e.value.code == -1
-    s.set_costs(torch.tensor(ilp.cost, dtype=torch.float64, device="cuda")) if hasattr(s, "set_costs") else \
-        B.bddmp_solver_set_costs(s.h, torch.tensor(ilp.cost, dtype=torch.float64, device="cuda"))
+    B.bddmp_solver_set_costs(s.h, torch.tensor(ilp.cost, dtype=torch.float64, device="cuda"))
     with pytest.raises(B.BddmpError) as e:
         s.instance_bounds()
     assert e.value.code == -7

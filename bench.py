@@ -334,6 +334,15 @@ def main():
                "s_per_iter": cpu_s / done}
         del o
 
+    # primal heuristic (Sec. 4, host) from the last step's total min-marginal differences
+    t = time.perf_counter()
+    Mh = Mv[:int(st.n_vars)].cpu().numpy()
+    xs, obj_s, feas_s, implied_s = plan.primal_search(Mh, 0)
+    search = {"score": "|M_i|", "feasible": bool(feas_s), "objective": obj_s if feas_s else None,
+              "implied_by_propagation": int(implied_s), "host_s": time.perf_counter() - t,
+              "sign_rounding": {"objective": obj, "violated_rows": int(nviol)}}
+    log(f"[bench] primal search: {search}")
+
     smoothed = None
     if not args.no_smoothed:
         smoothed = smoothed_vs_plain(args, B, I, torch)
@@ -356,7 +365,7 @@ def main():
                    "bound_dtype": "f64"},
         "hbm_gbps_per_iter": gbps_iter, "iter_ms": iter_ms, "model_bytes_per_iter": iter_bytes,
         "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit, "lb_final": lb_star, "lb_0": float(hist[0]),
-        "primal_obj": obj, "primal_violated_rows": int(nviol),
+        "primal_obj": obj, "primal_violated_rows": int(nviol), "primal_search": search,
         "host_build_s": {"generate": gen_s, "plan": plan_s, "bind_upload": bind_s},
         "roofline": roofline, "cpu_baseline": cpu,
         "batched_vs_plain": batched,

@@ -159,6 +159,33 @@ int32_t bddmp_plan_create_batch(const bddmp_problem *const *probs, int32_t n_ins
  */
 int32_t bddmp_plan_instances(const bddmp_plan *plan, int64_t *var_off, int64_t *row_off, int64_t *inc_off);
 
+/*
+ * Primal heuristic (Sec. 4; App. "Primal heuristic", Alg. "Primal-Heuristic" with Alg.
+ * "Restriction-Propagation" and the BDD manipulations of App. "Variable fixations"): variables are
+ * fixed to their preferred values beta_i = [M_i <= 0] (eq. "preferred-variable-value") in
+ * descending order of the score (score_mode 0: |M_i|; 1: -M_i; 2: sign(R_i) M_i with R_i the
+ * search space reduction coefficient, eq. "search-space-reduction-coeff"; ties by index). Each
+ * fixation restricts every diagram of the variable and propagates the values the restricted
+ * diagrams imply; when that empties a feasible set the other value is tried, and when both fail
+ * the search stops (*feasible = 0; undecided variables are -1 in x). Variables in no row take
+ * [c_i < 0]. M: host float [n_vars] total min-marginal differences (e.g. from
+ * bddmp_solver_round_primal); x: host int8 [n_vars]; *obj = c^T x over the variables set to 1;
+ * *n_implied: variables fixed by propagation rather than chosen. Host only.
+ */
+int32_t bddmp_plan_primal_search(const bddmp_plan *plan, const float *M, int32_t score_mode, int8_t *x, double *obj,
+                                 int32_t *feasible, int64_t *n_implied);
+
+/*
+ * One row's diagram after fixing variables (App. "Variable fixations": (1-beta)-arcs of the
+ * variable's level to FALSE, nodes cut off from the root removed forward, nodes without a path to
+ * TRUE removed backward with their in-arcs sent to FALSE). vars/vals: host [n_fix], fixations of
+ * variables outside the row are ignored. alive (uint8), lo, hi: host [nodes of the row] in
+ * canonical node order, children as in-level indices, -1 FALSE, -2 TRUE; *feasible = 0 when the
+ * restricted feasible set is empty. Host only.
+ */
+int32_t bddmp_plan_restrict_row(const bddmp_plan *plan, int32_t row, int32_t n_fix, const int32_t *vars,
+                                const int8_t *vals, uint8_t *alive, int32_t *lo, int32_t *hi, int32_t *feasible);
+
 /* Sizes of the plan (host). */
 int32_t bddmp_plan_stats(const bddmp_plan *plan, bddmp_stats *out);
 

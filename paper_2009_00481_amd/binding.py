@@ -67,6 +67,8 @@ SIGNATURES = {
     "bddmp_plan_create": (_I32, [_P, C.POINTER(Options), C.POINTER(_P)]),
     "bddmp_plan_create_batch": (_I32, [_P, _I32, C.POINTER(Options), C.POINTER(_P)]),
     "bddmp_plan_instances": (_I32, [_P, _P, _P, _P]),
+    "bddmp_plan_primal_search": (_I32, [_P, _P, _I32, _P, C.POINTER(_D), C.POINTER(_I32), C.POINTER(_I64)]),
+    "bddmp_plan_restrict_row": (_I32, [_P, _I32, _I32, _P, _P, _P, _P, _P, C.POINTER(_I32)]),
     "bddmp_plan_stats": (_I32, [_P, C.POINTER(Stats)]),
     "bddmp_plan_export_order": (_I32, [_P, _P]),
     "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
@@ -194,6 +196,29 @@ def bddmp_plan_instances(plan, n_inst: int):
     c = np.zeros(n_inst + 1, np.int64)
     _check(lib().bddmp_plan_instances(plan, _ptr(v), _ptr(r), _ptr(c)))
     return v, r, c
+
+
+def bddmp_plan_primal_search(plan, M, n: int, score_mode: int = 0):
+    M = np.ascontiguousarray(M, np.float32)
+    assert M.shape == (n,)
+    x = np.zeros(max(n, 1), np.int8)
+    obj, feas, imp = C.c_double(), C.c_int32(), C.c_int64()
+    _check(lib().bddmp_plan_primal_search(plan, _ptr(M), int(score_mode), _ptr(x), C.byref(obj), C.byref(feas),
+                                          C.byref(imp)))
+    return x[:n], obj.value, bool(feas.value), imp.value
+
+
+def bddmp_plan_restrict_row(plan, row: int, n_nodes: int, vars_, vals):
+    vars_ = np.ascontiguousarray(vars_, np.int32)
+    vals = np.ascontiguousarray(vals, np.int8)
+    alive = np.zeros(max(n_nodes, 1), np.uint8)
+    lo = np.zeros(max(n_nodes, 1), np.int32)
+    hi = np.zeros(max(n_nodes, 1), np.int32)
+    feas = C.c_int32()
+    _check(lib().bddmp_plan_restrict_row(plan, int(row), int(vars_.shape[0]), _ptr(vars_) if vars_.size else None,
+                                         _ptr(vals) if vals.size else None, _ptr(alive), _ptr(lo), _ptr(hi),
+                                         C.byref(feas)))
+    return alive[:n_nodes].astype(bool), lo[:n_nodes], hi[:n_nodes], bool(feas.value)
 
 
 def bddmp_plan_stats(plan) -> Stats:
@@ -384,6 +409,10 @@ class Plan:
             self.n = problem.n
             self.h = bddmp_plan_create(problem.h, o)
         self.stats = bddmp_plan_stats(self.h)
+
+    def primal_search(self, M, score_mode: int = 0):
+        """(x, objective, feasible, n_implied) of the primal heuristic from total differences M."""
+        return bddmp_plan_primal_search(self.h, M, self.n, score_mode)
 
     def instances(self):
         """(var_off, row_off, inc_off), each [n_instances + 1]."""

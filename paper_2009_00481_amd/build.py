@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BDDMP_ARCH", "gfx950")
 
-HOST_SOURCES = ["builder.cpp", "plan.cpp", "capi.cpp"]
+HOST_SOURCES = ["primal.cpp", "builder.cpp", "plan.cpp", "capi.cpp"]
 HIP_SOURCES = ["kernels.hip", "smooth.hip", "solver.hip"]
 # packed fp32 instructions stay off in every device build
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -191,6 +191,18 @@ int32_t bddmp_plan_instances(const bddmp_plan *h, int64_t *var_off, int64_t *row
   return BDDMP_OK;
 }
 
+int32_t bddmp_plan_primal_search(const bddmp_plan *h, const float *M, int32_t score_mode, int8_t *x, double *obj,
+                                 int32_t *feasible, int64_t *n_implied) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  return guarded([&] { return bddmp::primal_search(h->plan, M, score_mode, x, obj, feasible, n_implied); });
+}
+
+int32_t bddmp_plan_restrict_row(const bddmp_plan *h, int32_t row, int32_t n_fix, const int32_t *vars,
+                                const int8_t *vals, uint8_t *alive, int32_t *lo, int32_t *hi, int32_t *feasible) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  return guarded([&] { return bddmp::restrict_row(h->plan, row, n_fix, vars, vals, alive, lo, hi, feasible); });
+}
+
 int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   if (!h || !out) return set_error(BDDMP_INVALID_ARG, "null plan or out");
   const bddmp::Plan &P = h->plan;

@@ -166,14 +166,15 @@ int32_t bddmp_plan_instances(const bddmp_plan *plan, int64_t *var_off, int64_t *
  * descending order of the score (score_mode 0: |M_i|; 1: -M_i; 2: sign(R_i) M_i with R_i the
  * search space reduction coefficient, eq. "search-space-reduction-coeff"; ties by index). Each
  * fixation restricts every diagram of the variable and propagates the values the restricted
- * diagrams imply; when that empties a feasible set the other value is tried, and when both fail
- * the search stops (*feasible = 0; undecided variables are -1 in x). Variables in no row take
- * [c_i < 0]. M: host float [n_vars] total min-marginal differences (e.g. from
- * bddmp_solver_round_primal); x: host int8 [n_vars]; *obj = c^T x over the variables set to 1;
- * *n_implied: variables fixed by propagation rather than chosen. Host only.
+ * diagrams imply; when that empties a feasible set the other value is tried; when both fail the
+ * search returns to the latest fixation whose other value is untried (depth-first search, Sec. 4).
+ * It stops with a solution or after max_dead_ends dead ends (*feasible = 0; undecided variables
+ * are -1 in x). Variables in no row take [c_i < 0]. M: host float [n_vars] total min-marginal
+ * differences (e.g. from bddmp_solver_round_primal); x: host int8 [n_vars]; *obj = c^T x over the
+ * variables set to 1; *n_implied: variables fixed by propagation rather than chosen. Host only.
  */
-int32_t bddmp_plan_primal_search(const bddmp_plan *plan, const float *M, int32_t score_mode, int8_t *x, double *obj,
-                                 int32_t *feasible, int64_t *n_implied);
+int32_t bddmp_plan_primal_search(const bddmp_plan *plan, const float *M, int32_t score_mode, int64_t max_dead_ends,
+                                 int8_t *x, double *obj, int32_t *feasible, int64_t *n_implied);
 
 /*
  * One row's diagram after fixing variables (App. "Variable fixations": (1-beta)-arcs of the

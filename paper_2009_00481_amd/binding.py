@@ -67,7 +67,7 @@ SIGNATURES = {
     "bddmp_plan_create": (_I32, [_P, C.POINTER(Options), C.POINTER(_P)]),
     "bddmp_plan_create_batch": (_I32, [_P, _I32, C.POINTER(Options), C.POINTER(_P)]),
     "bddmp_plan_instances": (_I32, [_P, _P, _P, _P]),
-    "bddmp_plan_primal_search": (_I32, [_P, _P, _I32, _P, C.POINTER(_D), C.POINTER(_I32), C.POINTER(_I64)]),
+    "bddmp_plan_primal_search": (_I32, [_P, _P, _I32, _I64, _P, C.POINTER(_D), C.POINTER(_I32), C.POINTER(_I64)]),
     "bddmp_plan_restrict_row": (_I32, [_P, _I32, _I32, _P, _P, _P, _P, _P, C.POINTER(_I32)]),
     "bddmp_plan_stats": (_I32, [_P, C.POINTER(Stats)]),
     "bddmp_plan_export_order": (_I32, [_P, _P]),
@@ -198,13 +198,13 @@ def bddmp_plan_instances(plan, n_inst: int):
     return v, r, c
 
 
-def bddmp_plan_primal_search(plan, M, n: int, score_mode: int = 0):
+def bddmp_plan_primal_search(plan, M, n: int, score_mode: int = 0, max_dead_ends: int = 100000):
     M = np.ascontiguousarray(M, np.float32)
     assert M.shape == (n,)
     x = np.zeros(max(n, 1), np.int8)
     obj, feas, imp = C.c_double(), C.c_int32(), C.c_int64()
-    _check(lib().bddmp_plan_primal_search(plan, _ptr(M), int(score_mode), _ptr(x), C.byref(obj), C.byref(feas),
-                                          C.byref(imp)))
+    _check(lib().bddmp_plan_primal_search(plan, _ptr(M), int(score_mode), int(max_dead_ends), _ptr(x), C.byref(obj),
+                                          C.byref(feas), C.byref(imp)))
     return x[:n], obj.value, bool(feas.value), imp.value
 
 
@@ -410,9 +410,9 @@ class Plan:
             self.h = bddmp_plan_create(problem.h, o)
         self.stats = bddmp_plan_stats(self.h)
 
-    def primal_search(self, M, score_mode: int = 0):
+    def primal_search(self, M, score_mode: int = 0, max_dead_ends: int = 100000):
         """(x, objective, feasible, n_implied) of the primal heuristic from total differences M."""
-        return bddmp_plan_primal_search(self.h, M, self.n, score_mode)
+        return bddmp_plan_primal_search(self.h, M, self.n, score_mode, max_dead_ends)
 
     def instances(self):
         """(var_off, row_off, inc_off), each [n_instances + 1]."""

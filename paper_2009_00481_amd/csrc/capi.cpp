@@ -191,10 +191,13 @@ int32_t bddmp_plan_instances(const bddmp_plan *h, int64_t *var_off, int64_t *row
   return BDDMP_OK;
 }
 
-int32_t bddmp_plan_primal_search(const bddmp_plan *h, const float *M, int32_t score_mode, int8_t *x, double *obj,
-                                 int32_t *feasible, int64_t *n_implied) {
+int32_t bddmp_plan_primal_search(const bddmp_plan *h, const float *M, int32_t score_mode, int64_t max_dead_ends,
+                                 int8_t *x, double *obj, int32_t *feasible, int64_t *n_implied) {
   if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
-  return guarded([&] { return bddmp::primal_search(h->plan, M, score_mode, x, obj, feasible, n_implied); });
+  if (max_dead_ends < 0) return set_error(BDDMP_INVALID_ARG, "negative dead-end budget");
+  return guarded([&] {
+    return bddmp::primal_search(h->plan, M, score_mode, max_dead_ends, x, obj, feasible, n_implied);
+  });
 }
 
 int32_t bddmp_plan_restrict_row(const bddmp_plan *h, int32_t row, int32_t n_fix, const int32_t *vars,

@@ -156,8 +156,8 @@ struct Plan {
 };
 
 int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &out);
-int32_t primal_search(const Plan &P, const float *M, int32_t mode, int8_t *x, double *obj, int32_t *feasible,
-                      int64_t *implied);
+int32_t primal_search(const Plan &P, const float *M, int32_t mode, int64_t max_dead_ends, int8_t *x, double *obj,
+                      int32_t *feasible, int64_t *implied);
 int32_t restrict_row(const Plan &P, int32_t row, int32_t n_fix, const int32_t *vars, const int8_t *vals,
                      uint8_t *alive, int32_t *lo, int32_t *hi, int32_t *feasible);
 void greedy_colour_order(const Problem &p, std::vector<int32_t> &order);

@@ -9,9 +9,11 @@
 // restricted feasible set. After the changes, a level whose remaining arcs all carry one label
 // implies that value for its variable (the set F of Alg. "Restriction-Propagation").
 //
-// The search follows Alg. "Primal-Heuristic": fix the open variable of largest score to its
-// preferred value and propagate; if that empties a feasible set, undo and try the other value; if
-// that fails too the search ends without a solution. Every change goes on an undo trail.
+// The search follows Alg. "Primal-Heuristic" as a depth-first search: fix the open variable of
+// largest score to its preferred value and propagate; if that empties a feasible set, undo and try
+// the other value; when both fail, return to the latest fixation whose other value is untried (the
+// backtracking the text of Sec. 4 describes) until a complete solution or a budget of dead ends
+// is reached. Every change goes on an undo trail.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -254,8 +256,8 @@ struct Restrictor {
 
 }  // namespace
 
-int32_t primal_search(const Plan &P, const float *M, int32_t mode, int8_t *x, double *obj, int32_t *feasible,
-                      int64_t *implied) {
+int32_t primal_search(const Plan &P, const float *M, int32_t mode, int64_t max_dead_ends, int8_t *x, double *obj,
+                      int32_t *feasible, int64_t *implied) {
   if (!M || !x) return set_error(BDDMP_INVALID_ARG, "null M or x");
   if (mode < 0 || mode > 2) return set_error(BDDMP_INVALID_ARG, "score mode must be 0, 1 or 2");
   Restrictor R(P);
@@ -296,27 +298,65 @@ int32_t primal_search(const Plan &P, const float *M, int32_t mode, int8_t *x, do
   std::vector<int32_t> order(static_cast<size_t>(n));
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return score[a] > score[b]; });
-  int64_t n_implied = 0, n_chosen = 0;
-  bool ok = true;
-  for (int32_t i : order) {
-    if (R.value[i] >= 0) continue;
-    if (R.var_ptr[i] == R.var_ptr[i + 1]) {  // in no row: its own best value (eq. "preferred-variable-value")
+  // variables in no row take their own best value (eq. "preferred-variable-value")
+  int64_t n_free = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (R.var_ptr[i] == R.var_ptr[i + 1]) {
       R.set_value(i, int8_t(P.cost[i] < 0));
-      continue;
+      ++n_free;
     }
+  struct Decision {
+    int32_t pos;   // position in the order
+    int8_t value;  // value in force
+    bool last;     // no other value left to try
+    size_t mark;   // trail length before the fixation
+  };
+  std::vector<Decision> stack;
+  int64_t dead_ends = 0;
+  bool ok = true;
+  int32_t pos = 0;
+  for (;;) {
+    while (pos < n && R.value[order[pos]] >= 0) ++pos;
+    if (pos == n) break;
+    const int32_t i = order[pos];
     const int beta = M[i] <= 0.0f ? 1 : 0;
     const size_t mark = R.trail.size();
-    ++n_chosen;
-    if (R.propagate(i, beta)) continue;
+    if (R.propagate(i, beta)) {
+      stack.push_back({pos, int8_t(beta), false, mark});
+      continue;
+    }
     R.undo_to(mark);
-    if (R.propagate(i, 1 - beta)) continue;
+    if (R.propagate(i, 1 - beta)) {
+      stack.push_back({pos, int8_t(1 - beta), true, mark});
+      continue;
+    }
     R.undo_to(mark);
-    ok = false;
-    break;
+    // dead end: back to the latest fixation with an untried value
+    ++dead_ends;
+    bool resumed = false;
+    while (!stack.empty() && dead_ends <= max_dead_ends) {
+      const Decision d = stack.back();
+      stack.pop_back();
+      R.undo_to(d.mark);
+      if (d.last) continue;
+      const int32_t vi = order[d.pos];
+      if (R.propagate(vi, 1 - d.value)) {
+        stack.push_back({d.pos, int8_t(1 - d.value), true, d.mark});
+        pos = d.pos;
+        resumed = true;
+        break;
+      }
+      R.undo_to(d.mark);
+      ++dead_ends;
+    }
+    if (!resumed) {
+      ok = false;
+      break;
+    }
   }
   int64_t fixed = 0;
   for (int32_t i = 0; i < n; ++i) fixed += R.value[i] >= 0;
-  n_implied = fixed - n_chosen;
+  const int64_t n_implied = fixed - int64_t(stack.size()) - n_free;
   double o = 0.0;
   for (int32_t i = 0; i < n; ++i) {
     x[i] = R.value[i] < 0 ? int8_t(-1) : R.value[i];

@@ -150,3 +150,22 @@ def test_search_errors():
     with pytest.raises(B.BddmpError) as e:
         B.bddmp_plan_restrict_row(plan.h, plan.stats.n_bdds, 4, [0], [1])
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("seed,mode", [(7, 1), (27, 0), (41, 0), (42, 2), (53, 2)])
+def test_search_backtracks_past_dead_ends(seed, mode):
+    """Instances where the dive with one-value retries dead-ends (no solution with a budget of 0
+    dead ends) while the depth-first search finds one; library and oracle agree on both."""
+    ilp = I.random_ilp(24, 18, kmin=2, kmax=6, cmax=2, seed=seed)
+    o = Oracle(ilp)
+    o.init()
+    o.iterate(3)
+    M, _, _, _ = o.round()
+    plan = B.Plan(B.Problem.from_ilp(ilp))
+    for budget in (0, 100000):
+        x, obj, feas, _ = plan.primal_search(M.astype(np.float32), mode, max_dead_ends=budget)
+        xr, objr, feasr = primal_heuristic(ilp, M, mode, max_dead_ends=budget)
+        assert feas == feasr and np.array_equal(x, xr), budget
+        assert feas == (budget > 0)
+        if feas:
+            assert _holds(ilp, x.astype(np.int64))

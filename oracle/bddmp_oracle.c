@@ -96,6 +96,12 @@ typedef struct {
   REAL *mf;     /* forward messages (cost of the best root-to-node path) */
   REAL *mb;     /* backward messages (cost of the best node-to-TOP path) */
   REAL *lam;    /* [k] lambda^j of each level's variable */
+  /* Sec. 6 split (NULL without one): cut[l] = 1 when levels l and l+1 lie in different variable
+   * intervals. For an arc (u, beta) leaving a cut level, index 2u+beta: mux = mu of its copy-arc
+   * (the arc to TOP ending the sub-BDD before the cut), mue = mu of the arc itself (entering the
+   * sub-BDD after the cut), dfw / dbw = the last forward / backward copy-arc updates. */
+  unsigned char *cut;
+  REAL *mux, *mue, *dfw, *dbw;
 } bdd_t;
 
 static int cmp_ll(const void *a, const void *b) {
@@ -259,6 +265,7 @@ done:
 static void free_bdd(bdd_t *B) {
   free(B->var); free(B->first); free(B->lo); free(B->hi);
   free(B->mf); free(B->mb); free(B->lam);
+  free(B->cut); free(B->mux); free(B->mue); free(B->dfw); free(B->dbw);
 }
 
 /* ---------------------------------------------------------------------------
@@ -275,11 +282,32 @@ static REAL child_mb(const REAL *mb, const bdd_t *B, int l, int c) {
   return mb[B->first[l + 1] + c];
 }
 
+/* backward value behind arc (u, beta) of level l (u a node index of the diagram): the child's
+ * backward message, or, where the diagram is cut after level l (Sec. 6, Def. "Sub-BDD"), the
+ * cost mu of the arc's copy-arc into TOP, which ends the sub-BDD before the cut. */
+static REAL behind(const bdd_t *B, const REAL *mb, int l, int u, int beta) {
+  int c = beta ? B->hi[u] : B->lo[u];
+  if (B->cut && B->cut[l] && c != BOT) return B->mux[2 * u + beta];
+  return child_mb(mb, B, l, c);
+}
+
 /* Alg. "Forward BDD update step" at level l: m_fwd(v) = min over in-arcs uv of m_fwd(u) + theta_uv;
- * the root has m_fwd = 0. */
+ * the root has m_fwd = 0. After a cut the tails of the in-arcs are roots of the sub-BDD (m_fwd
+ * 0) and each in-arc costs its copy dual mu alone (its lambda belongs to the sub-BDD before). */
 static void forward_step(const bdd_t *B, REAL *mf, int l) {
   if (l == 0) { mf[B->first[0]] = 0; return; }
   for (int v = B->first[l]; v < B->first[l + 1]; ++v) mf[v] = REAL_INF;
+  if (B->cut && B->cut[l - 1]) {
+    for (int u = B->first[l - 1]; u < B->first[l]; ++u) {
+      int c[2] = {B->lo[u], B->hi[u]};
+      for (int beta = 0; beta < 2; ++beta) {
+        if (c[beta] < 0) continue;
+        int v = B->first[l] + c[beta];
+        mf[v] = rmin(mf[v], B->mue[2 * u + beta]);
+      }
+    }
+    return;
+  }
   for (int u = B->first[l - 1]; u < B->first[l]; ++u) {
     int c[2] = {B->lo[u], B->hi[u]};
     for (int beta = 0; beta < 2; ++beta) {
@@ -293,7 +321,7 @@ static void forward_step(const bdd_t *B, REAL *mf, int l) {
 /* Alg. "Backward BDD update step" at level l: m_bwd(v) = min over the two out-arcs of m_bwd(child) + theta. */
 static void backward_step(const bdd_t *B, REAL *mb, int l) {
   for (int u = B->first[l]; u < B->first[l + 1]; ++u)
-    mb[u] = rmin(child_mb(mb, B, l, B->lo[u]) + theta(B, l, 0), child_mb(mb, B, l, B->hi[u]) + theta(B, l, 1));
+    mb[u] = rmin(behind(B, mb, l, u, 0) + theta(B, l, 0), behind(B, mb, l, u, 1) + theta(B, l, 1));
 }
 
 /* eqs. "arc-marginal" and "marginal-aggregation": m^beta = min over beta-arcs uv leaving level l of
@@ -301,9 +329,8 @@ static void backward_step(const bdd_t *B, REAL *mb, int l) {
 static void level_min_marginals(const bdd_t *B, const REAL *mf, const REAL *mb, int l, REAL *m0, REAL *m1) {
   REAL best[2] = {REAL_INF, REAL_INF};
   for (int u = B->first[l]; u < B->first[l + 1]; ++u) {
-    int c[2] = {B->lo[u], B->hi[u]};
     for (int beta = 0; beta < 2; ++beta) {
-      REAL arc = (mf[u] + theta(B, l, beta)) + child_mb(mb, B, l, c[beta]);
+      REAL arc = (mf[u] + theta(B, l, beta)) + behind(B, mb, l, u, beta);
       best[beta] = rmin(best[beta], arc);
     }
   }
@@ -358,6 +385,10 @@ typedef struct orc_state {
   double chk[4];
   REAL *dbuf;                /* scratch of max |J_i| differences */
   int maxJ;
+  int split_k;               /* Sec. 6 variable intervals (0: no split) */
+  REAL gamma;                /* copy-arc step size */
+  int *intv;                 /* [n] interval of each variable */
+  long long n_cuts, n_copy;  /* cut levels and copy-arc pairs */
 } orc_state;
 
 void orc_destroy(orc_state *S) {
@@ -366,7 +397,7 @@ void orc_destroy(orc_state *S) {
     for (int j = 0; j < S->m; ++j) free_bdd(&S->bdd[j]);
   free(S->bdd); free(S->cost); free(S->row_ptr); free(S->coef); free(S->rhs); free(S->col);
   free(S->sense); free(S->order); free(S->canon); free(S->ncanon); free(S->inc_ptr);
-  free(S->inc_bdd); free(S->inc_lvl); free(S->dbuf);
+  free(S->inc_bdd); free(S->inc_lvl); free(S->dbuf); free(S->intv);
   free(S);
 }
 
@@ -504,10 +535,29 @@ void orc_structure(const orc_state *S, int *level_width, int *level_var, int *lo
   }
 }
 
+/* E of the sub-BDD that starts after the cut at level l (Sec. 6): the best path enters through
+ * one arc uv, costing its copy dual mu plus the backward message of v. */
+static REAL cut_energy(const bdd_t *B, int l) {
+  REAL e = REAL_INF;
+  for (int u = B->first[l]; u < B->first[l + 1]; ++u) {
+    int c[2] = {B->lo[u], B->hi[u]};
+    for (int beta = 0; beta < 2; ++beta)
+      if (c[beta] >= 0) e = rmin(e, B->mue[2 * u + beta] + B->mb[B->first[l + 1] + c[beta]]);
+  }
+  return e;
+}
+
+/* The dual bound: sum of E over all (sub-)BDDs, plus the variables in no row. */
 static double lower_bound(const orc_state *S) {
   double lb = 0.0;
-  for (int j = 0; j < S->m; ++j)
-    if (S->bdd[j].k) lb += (double)S->bdd[j].mb[S->bdd[j].first[0]];
+  for (int j = 0; j < S->m; ++j) {
+    const bdd_t *B = &S->bdd[j];
+    if (!B->k) continue;
+    lb += (double)B->mb[B->first[0]];
+    if (B->cut)
+      for (int l = 0; l + 1 < B->k; ++l)
+        if (B->cut[l]) lb += (double)cut_energy(B, l);
+  }
   return lb + S->lb_const;
 }
 
@@ -627,7 +677,11 @@ static int process_variable(orc_state *S, int i, int fwd) {
  * messages by backward steps from the last level up ("after initialization of all messages",
  * Prop. "correctness"). check_flags selects the per-update self checks (tiny inputs only).
  */
+static void reset_copy_duals(orc_state *S);
+
 int orc_init(orc_state *S, int check_flags) {
+  if (S->split_k && check_flags) return fail(ORC_INVALID_ARG, "self checks apply to the unsplit decomposition", check_flags);
+  reset_copy_duals(S);
   S->flags = check_flags;
   for (int k = 0; k < 4; ++k) S->chk[k] = 0.0;
   for (int i = 0; i < S->n; ++i) {
@@ -655,8 +709,13 @@ int orc_set_lambda(orc_state *S, const double *lam) {
   return ORC_OK;
 }
 
+static void copy_update_forward(orc_state *S);
+static void copy_update_backward(orc_state *S);
+
 /* iters rounds of a forward pass over order[0..n-1] then a backward pass over order[n-1..0];
- * lb_trace[t] receives the bound after round t. */
+ * lb_trace[t] receives the bound after round t. With a split (Sec. 6, Alg. "Parallel min-marginal
+ * averaging") each pass is followed by the copy-arc updates; the intervals are independent
+ * within a pass, so visiting all variables in processing order is the parallel pass. */
 int orc_iterate(orc_state *S, int iters, double *lb_trace) {
   if (!S->inited) return fail(ORC_BAD_STATE, "orc_init first", 0);
   for (int t = 0; t < iters; ++t) {
@@ -664,10 +723,12 @@ int orc_iterate(orc_state *S, int iters, double *lb_trace) {
       int rc = process_variable(S, S->order[r], 1);
       if (rc) return rc;
     }
+    if (S->split_k) copy_update_forward(S);
     for (int r = S->n - 1; r >= 0; --r) {
       int rc = process_variable(S, S->order[r], 0);
       if (rc) return rc;
     }
+    if (S->split_k) copy_update_backward(S);
     S->lb = lower_bound(S);
     if (lb_trace) lb_trace[t] = S->lb;
   }
@@ -768,6 +829,180 @@ void orc_count_solutions(const orc_state *S, double *count) {
       }
     count[j] = c[B->first[0]];
     free(c);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Sec. 6: variable intervals, sub-BDDs and copy-arc duals
+ *
+ * The processing order is cut into K intervals of about equal node count: a variable counts the
+ * nodes of its levels over all its rows, and the variable at order position r (c_r nodes before
+ * it, N in total) lies in interval floor(K c_r / N). A row's diagram is cut between consecutive
+ * levels in different intervals (Def. "Sub-BDD"): the sub-BDD before the cut ends with arcs into
+ * TOP (the copy-arcs), the sub-BDD after it starts at the same arcs, whose tails act as its
+ * roots. Each pair carries a dual: mu_bar on the copy-arc, mu on the arc; their sum stays <= 0.
+ * Readings: the arc's lambda is counted in the sub-BDD before the cut (the tail's variable lies
+ * in that interval), so the entering arc costs mu alone; the minimum in the copy-arc updates
+ * runs over the pairs of one cut (the arcs a sub-BDD ends or starts with), which keeps every
+ * difference non-negative as Prop. "correctness-parallel" uses; the forward update takes the
+ * arc-marginals after the pass (with the last level's updated lambda), the backward one the
+ * backward messages after the pass; the bound is taken after the backward copy update.
+ * ------------------------------------------------------------------------- */
+
+static void reset_copy_duals(orc_state *S) {
+  if (!S->split_k) return;
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    if (!B->mux) continue;
+    size_t na = (size_t)2 * (size_t)B->first[B->k];
+    for (size_t q = 0; q < na; ++q) B->mux[q] = B->mue[q] = B->dfw[q] = B->dbw[q] = 0;
+  }
+}
+
+/* after the forward pass: for the copy-arcs closing each cut's earlier sub-BDD,
+ * delta_fwd = m(copy-arc) - min over the cut's copy-arcs, mu_bar <- mu_bar - g delta_fwd + g delta_bwd */
+static void copy_update_forward(orc_state *S) {
+  REAL g = S->gamma;
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    if (!B->cut) continue;
+    for (int l = 0; l + 1 < B->k; ++l) {
+      if (!B->cut[l]) continue;
+      REAL mn = REAL_INF;
+      for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          if ((beta ? B->hi[u] : B->lo[u]) < 0) continue;
+          int q = 2 * u + beta;
+          mn = rmin(mn, (B->mf[u] + theta(B, l, beta)) + B->mux[q]);
+        }
+      for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          if ((beta ? B->hi[u] : B->lo[u]) < 0) continue;
+          int q = 2 * u + beta;
+          REAL m = (B->mf[u] + theta(B, l, beta)) + B->mux[q];
+          B->dfw[q] = m - mn;
+          B->mux[q] = (B->mux[q] - g * B->dfw[q]) + g * B->dbw[q];
+        }
+    }
+  }
+}
+
+/* after the backward pass: for the arcs opening each cut's later sub-BDD,
+ * delta_bwd = m(arc) - min over the cut's arcs, mu <- mu - g delta_bwd + g delta_fwd */
+static void copy_update_backward(orc_state *S) {
+  REAL g = S->gamma;
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    if (!B->cut) continue;
+    for (int l = 0; l + 1 < B->k; ++l) {
+      if (!B->cut[l]) continue;
+      REAL mn = REAL_INF;
+      for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          int c = beta ? B->hi[u] : B->lo[u];
+          if (c < 0) continue;
+          mn = rmin(mn, B->mue[2 * u + beta] + B->mb[B->first[l + 1] + c]);
+        }
+      for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          int c = beta ? B->hi[u] : B->lo[u];
+          if (c < 0) continue;
+          int q = 2 * u + beta;
+          REAL m = B->mue[q] + B->mb[B->first[l + 1] + c];
+          B->dbw[q] = m - mn;
+          B->mue[q] = (B->mue[q] - g * B->dbw[q]) + g * B->dfw[q];
+        }
+    }
+  }
+}
+
+/* Split every row at the boundaries of K variable intervals (K <= 1: no split) with copy-arc step
+ * size gamma in (0, 1]. Call before orc_init; the duals start at 0. */
+int orc_split(orc_state *S, int K, double gamma) {
+  if (K < 0 || !(gamma > 0.0 && gamma <= 1.0)) return fail(ORC_INVALID_ARG, "K >= 0 and 0 < gamma <= 1", K);
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    free(B->cut); free(B->mux); free(B->mue); free(B->dfw); free(B->dbw);
+    B->cut = NULL; B->mux = B->mue = B->dfw = B->dbw = NULL;
+  }
+  free(S->intv);
+  S->intv = NULL;
+  S->split_k = 0;
+  S->n_cuts = S->n_copy = 0;
+  S->inited = 0;
+  if (K <= 1) return ORC_OK;
+  S->split_k = K;
+  S->gamma = (REAL)gamma;
+  S->intv = (int *)calloc((size_t)(S->n ? S->n : 1), sizeof(int));
+  long long *cnt = (long long *)calloc((size_t)(S->n ? S->n : 1), sizeof(long long));
+  if (!S->intv || !cnt) { free(cnt); return ORC_NOMEM; }
+  long long total = 0;
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    for (int l = 0; l < B->k; ++l) cnt[B->var[l]] += B->first[l + 1] - B->first[l];
+  }
+  for (int i = 0; i < S->n; ++i) total += cnt[i];
+  long long before = 0;
+  for (int r = 0; r < S->n; ++r) {
+    int i = S->order[r];
+    S->intv[i] = total ? (int)((long long)K * before / total) : 0;
+    before += cnt[i];
+  }
+  free(cnt);
+  for (int j = 0; j < S->m; ++j) {
+    bdd_t *B = &S->bdd[j];
+    int any = 0;
+    for (int l = 0; l + 1 < B->k; ++l) any |= S->intv[B->var[l]] != S->intv[B->var[l + 1]];
+    if (!any) continue;
+    size_t na = (size_t)2 * (size_t)B->first[B->k];
+    B->cut = (unsigned char *)calloc((size_t)B->k, 1);
+    B->mux = (REAL *)calloc(na, sizeof(REAL));
+    B->mue = (REAL *)calloc(na, sizeof(REAL));
+    B->dfw = (REAL *)calloc(na, sizeof(REAL));
+    B->dbw = (REAL *)calloc(na, sizeof(REAL));
+    if (!B->cut || !B->mux || !B->mue || !B->dfw || !B->dbw) return ORC_NOMEM;
+    for (int l = 0; l + 1 < B->k; ++l)
+      if (S->intv[B->var[l]] != S->intv[B->var[l + 1]]) {
+        B->cut[l] = 1;
+        S->n_cuts++;
+        for (int u = B->first[l]; u < B->first[l + 1]; ++u) S->n_copy += (B->lo[u] >= 0) + (B->hi[u] >= 0);
+      }
+  }
+  return ORC_OK;
+}
+
+/* split summary: K, cut levels, copy-arc pairs; intv[n] (may be NULL) receives each variable's interval */
+void orc_split_info(const orc_state *S, long long *out3, int *intv) {
+  out3[0] = S->split_k;
+  out3[1] = S->n_cuts;
+  out3[2] = S->n_copy;
+  if (intv)
+    for (int i = 0; i < S->n; ++i) intv[i] = S->intv ? S->intv[i] : 0;
+}
+
+/* Copy duals per pair in canonical order (rows, cut levels ascending, tail node, arc label):
+ * mu_bar[n_copy], mu[n_copy]; row_of, level_of, node_of (in-level index), label_of may be NULL. */
+void orc_copy_duals(const orc_state *S, double *mu_bar, double *mu, int *row_of, int *level_of, int *node_of,
+                    int *label_of) {
+  long long q = 0;
+  for (int j = 0; j < S->m; ++j) {
+    const bdd_t *B = &S->bdd[j];
+    if (!B->cut) continue;
+    for (int l = 0; l + 1 < B->k; ++l) {
+      if (!B->cut[l]) continue;
+      for (int u = B->first[l]; u < B->first[l + 1]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          if ((beta ? B->hi[u] : B->lo[u]) < 0) continue;
+          int a = 2 * u + beta;
+          if (mu_bar) mu_bar[q] = (double)B->mux[a];
+          if (mu) mu[q] = (double)B->mue[a];
+          if (row_of) row_of[q] = j;
+          if (level_of) level_of[q] = l;
+          if (node_of) node_of[q] = u - B->first[l];
+          if (label_of) label_of[q] = beta;
+          ++q;
+        }
+    }
   }
 }
 
@@ -937,6 +1172,7 @@ static void init_lambda(orc_state *S) {
 
 /* Smoothed initialisation: lambda = c / |J_i|, smoothed backward messages, LB_alpha. */
 int orc_smooth_init(orc_state *S, double alpha) {
+  if (S->split_k) return fail(ORC_INVALID_ARG, "the smoothed variant runs on the unsplit decomposition", S->split_k);
   if (!(alpha > 0)) return fail(ORC_INVALID_ARG, "alpha must be positive", 0);
   S->flags = 0;
   init_lambda(S);
@@ -1108,6 +1344,7 @@ static void rev_update(const orc_state *S, int i, const REAL *d, const double *g
  * the costs: grad[n]; *lb_out = LB_alpha(T). Leaves the state after the T iterations.
  */
 int orc_smooth_grad(orc_state *S, double alpha, int T, double *grad, double *lb_out) {
+  if (S->split_k) return fail(ORC_INVALID_ARG, "the smoothed variant runs on the unsplit decomposition", S->split_k);
   int rc = orc_smooth_init(S, alpha);
   if (rc) return rc;
   long long I = S->n_inc, N = S->n_nodes;

@@ -61,6 +61,10 @@ def _lib(prec: str):
     L.orc_smooth_grad.restype = I
     L.orc_build_row.argtypes = [I, P, I, LL, LL, P, P, P, LL]
     L.orc_build_row.restype = LL
+    L.orc_split.argtypes = [P, I, D]
+    L.orc_split.restype = I
+    L.orc_split_info.argtypes = [P, P, P]
+    L.orc_copy_duals.argtypes = [P, P, P, P, P, P, P]
     _LIBS[prec] = L
     return L
 
@@ -77,7 +81,7 @@ def _check(L, rc):
 class Oracle:
     """One problem in the oracle: build, init, iterate, read results (canonical order)."""
 
-    def __init__(self, ilp, precision: str = "f64", node_budget: int = 0):
+    def __init__(self, ilp, precision: str = "f64", node_budget: int = 0, split: int = 0, gamma: float = 0.5):
         self.L = _lib(precision)
         self.precision = precision
         self._keep = [np.ascontiguousarray(ilp.cost, np.float64), np.ascontiguousarray(ilp.row_ptr, np.int64),
@@ -93,6 +97,23 @@ class Oracle:
         st = np.zeros(6, np.int64)
         self.L.orc_stats(self.h, _p(st))
         self.n, self.m, self.n_nodes, self.n_live_arcs, self.n_incidences, self.max_J = (int(v) for v in st)
+        if split > 1:
+            _check(self.L, self.L.orc_split(self.h, int(split), float(gamma)))
+
+    def split_info(self):
+        """(K, cut levels, copy-arc pairs, interval of each variable) of Sec. 6's split."""
+        out = np.zeros(3, np.int64)
+        intv = np.zeros(max(self.n, 1), np.int32)
+        self.L.orc_split_info(self.h, _p(out), _p(intv))
+        return int(out[0]), int(out[1]), int(out[2]), intv[:self.n]
+
+    def copy_duals(self):
+        """Per copy-arc pair in canonical order: dict of mu_bar, mu, row, level, node, label."""
+        n = self.split_info()[2]
+        mb, mu = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        r, l, u, b = (np.zeros(max(n, 1), np.int32) for _ in range(4))
+        self.L.orc_copy_duals(self.h, _p(mb), _p(mu), _p(r), _p(l), _p(u), _p(b))
+        return dict(mu_bar=mb[:n], mu=mu[:n], row=r[:n], level=l[:n], node=u[:n], label=b[:n])
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -74,6 +74,8 @@ typedef struct {
                              level nodes (0: 2048; the node-parallel path stages up to 2048 of each) */
   const char *tiling;     /* general-layer path by width class, "g0,g1,g2,g3" (NULL: default
                              "0,0,0,0"); see bddmp_solver_set_groups                             */
+  int32_t n_intervals;    /* Sec. 6 split: variable intervals per instance (0 or 1: no split)   */
+  float split_gamma;      /* copy-arc step size gamma in (0, 1] (0: default 0.5)                 */
 } bddmp_options;
 
 typedef struct {
@@ -86,6 +88,9 @@ typedef struct {
   int32_t bwd_contiguous;       /* 1 if every backward wave is a contiguous layer range    */
   int64_t fwd_tiles, bwd_tiles; /* workgroups per forward / backward pass                  */
   int32_t n_instances;          /* independent instances in the plan (1 unless batched)   */
+  int32_t n_intervals;          /* Sec. 6 variable intervals per instance (0: no split)    */
+  int64_t n_cuts;               /* cut levels (one per sub-BDD boundary)                   */
+  int64_t n_copy_pairs;         /* copy-arc pairs (live arcs leaving the cut levels)       */
 } bddmp_stats;
 
 typedef struct {
@@ -259,6 +264,21 @@ int32_t bddmp_solver_get_lambda(bddmp_solver *s, float *lam_dev);
 /* Replaces the multipliers from lam_dev (device, canonical order) and re-runs the initial
  * backward sweep (resume from a checkpoint); appends the new bound. Asynchronous. */
 int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
+
+/*
+ * Copy-arc state of a split plan (Sec. 6, Def. "Copy-arc", Alg. "Parallel min-marginal
+ * averaging"; bddmp_options.n_intervals > 1). One value per copy-arc pair (n_copy_pairs of
+ * bddmp_stats) in canonical order: rows, cut levels ascending, then the arc's tail node (in-level
+ * index) and label (0-arc first); only arcs not into BOT. mu_bar: dual of the copy-arc (into TOP)
+ * that ends the sub-BDD before the cut; mu: dual of the arc entering the sub-BDD after it; dfw /
+ * dbw: the last forward / backward updates delta (the next update of the other dual uses them).
+ * get: any pointer may be NULL (device arrays). Asynchronous.
+ * set: all four required; then the initial backward sweep re-runs (as bddmp_solver_set_lambda),
+ * appending a bound. Together with lambda this is a complete checkpoint of a split solver.
+ */
+int32_t bddmp_solver_get_copy_duals(bddmp_solver *s, float *mu_bar_dev, float *mu_dev, float *dfw_dev, float *dbw_dev);
+int32_t bddmp_solver_set_copy_duals(bddmp_solver *s, const float *mu_bar_dev, const float *mu_dev, const float *dfw_dev,
+                                    const float *dbw_dev);
 
 /*
  * Rounded primal from fresh min-marginals (Sec. 4): M_i = sum_j (m1_ij - m0_ij) in ascending row

@@ -32,7 +32,7 @@ class BddmpError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("order_mode", C.c_int32), ("hist_cap", C.c_int32), ("node_budget", C.c_int64),
                 ("stop_rel_impr", C.c_double), ("alpha", C.c_float), ("tile_work", C.c_int32),
-                ("tiling", C.c_char_p)]
+                ("tiling", C.c_char_p), ("n_intervals", C.c_int32), ("split_gamma", C.c_float)]
 
 
 class Stats(C.Structure):
@@ -40,7 +40,8 @@ class Stats(C.Structure):
                 ("n_arcs_bot", C.c_int64), ("n_incidences", C.c_int64), ("waves_fwd", C.c_int32),
                 ("waves_bwd", C.c_int32), ("device_bytes", C.c_int64), ("max_width", C.c_int32),
                 ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
-                ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32)]
+                ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32),
+                ("n_intervals", C.c_int32), ("n_cuts", C.c_int64), ("n_copy_pairs", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +83,8 @@ SIGNATURES = {
     "bddmp_solver_min_marginals": (_I32, [_P, _P, _P]),
     "bddmp_solver_get_lambda": (_I32, [_P, _P]),
     "bddmp_solver_set_lambda": (_I32, [_P, _P]),
+    "bddmp_solver_get_copy_duals": (_I32, [_P, _P, _P, _P, _P]),
+    "bddmp_solver_set_copy_duals": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_solver_round_primal": (_I32, [_P, _P, _P, C.POINTER(_D), C.POINTER(_I64)]),
     "bddmp_smooth_workspace_bytes": (_I32, [_P, _I32, C.POINTER(C.c_size_t)]),
     "bddmp_solver_smooth_run": (_I32, [_P, C.c_float, _I32, _P, C.c_size_t]),
@@ -294,6 +297,14 @@ def bddmp_solver_set_lambda(h, lam):
     _check(lib().bddmp_solver_set_lambda(h, _dptr(lam)))
 
 
+def bddmp_solver_get_copy_duals(h, mu_bar, mu, dfw, dbw):
+    _check(lib().bddmp_solver_get_copy_duals(h, _dptr(mu_bar), _dptr(mu), _dptr(dfw), _dptr(dbw)))
+
+
+def bddmp_solver_set_copy_duals(h, mu_bar, mu, dfw, dbw):
+    _check(lib().bddmp_solver_set_copy_duals(h, _dptr(mu_bar), _dptr(mu), _dptr(dfw), _dptr(dbw)))
+
+
 def bddmp_solver_round_primal(h, M, n: int):
     x = np.zeros(max(n, 1), np.int8)
     obj = C.c_double()
@@ -394,9 +405,11 @@ class Plan:
     """A plan for one problem, or for several independent ones (``problem`` a list: batched)."""
 
     def __init__(self, problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096,
-                 tiling: str | None = None, tile_work: int = 0):
+                 tiling: str | None = None, tile_work: int = 0, n_intervals: int = 0, split_gamma: float = 0.0):
         o = bddmp_options_default()
         o.tile_work = tile_work
+        o.n_intervals = n_intervals
+        o.split_gamma = split_gamma
         o.order_mode = order_mode
         o.node_budget = node_budget
         o.hist_cap = hist_cap
@@ -482,6 +495,19 @@ class Solver:
     def set_lambda(self, lam):
         assert lam.dtype == self.torch.float32 and lam.is_contiguous() and lam.numel() == self.n_incidences
         bddmp_solver_set_lambda(self.h, lam)
+
+    def copy_duals(self):
+        """Copy-arc state of a split plan per pair: (mu_bar, mu, delta_fwd, delta_bwd) device tensors."""
+        n = int(self.plan.stats.n_copy_pairs)
+        out = [self.torch.empty(max(n, 1), dtype=self.torch.float32, device=self.device) for _ in range(4)]
+        bddmp_solver_get_copy_duals(self.h, *out)
+        return tuple(t[:n] for t in out)
+
+    def set_copy_duals(self, mu_bar, mu, dfw, dbw):
+        n = int(self.plan.stats.n_copy_pairs)
+        for t in (mu_bar, mu, dfw, dbw):
+            assert t.dtype == self.torch.float32 and t.is_contiguous() and t.numel() >= n
+        bddmp_solver_set_copy_duals(self.h, mu_bar, mu, dfw, dbw)
 
     def round_primal(self):
         n = self.plan.n

@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BDDMP_ARCH", "gfx950")
 
 HOST_SOURCES = ["primal.cpp", "builder.cpp", "plan.cpp", "capi.cpp"]
-HIP_SOURCES = ["kernels.hip", "smooth.hip", "solver.hip"]
+HIP_SOURCES = ["kernels.hip", "smooth.hip", "split.hip", "solver.hip"]
 # packed fp32 instructions stay off in every device build
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]

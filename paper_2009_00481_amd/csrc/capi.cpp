@@ -226,6 +226,9 @@ int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   out->fwd_tiles = int64_t(P.fwd_tiles.size() / 2 + P.fwd_big.size() / 2);
   out->bwd_tiles = int64_t(P.bwd_tiles.size() / 2 + P.bwd_big.size() / 2);
   out->n_instances = int32_t(P.inst_var.size() - 1);
+  out->n_intervals = P.split_k;
+  out->n_cuts = P.n_cuts;
+  out->n_copy_pairs = P.n_copy;
   return BDDMP_OK;
 }
 
@@ -321,6 +324,20 @@ int32_t bddmp_solver_set_lambda(bddmp_solver *h, const float *lam_dev) {
   SOLVER_OR_FAIL(h);
   if (!lam_dev) return set_error(BDDMP_INVALID_ARG, "null input");
   return guarded([&] { return bddmp::solver_set_lambda(*h->s, lam_dev); });
+}
+
+int32_t bddmp_solver_get_copy_duals(bddmp_solver *h, float *mu_bar_dev, float *mu_dev, float *dfw_dev, float *dbw_dev) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_copy_duals(*h->s, true, mu_bar_dev, mu_dev, dfw_dev, dbw_dev); });
+}
+
+int32_t bddmp_solver_set_copy_duals(bddmp_solver *h, const float *mu_bar_dev, const float *mu_dev, const float *dfw_dev,
+                                    const float *dbw_dev) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] {
+    return bddmp::solver_copy_duals(*h->s, false, const_cast<float *>(mu_bar_dev), const_cast<float *>(mu_dev),
+                                    const_cast<float *>(dfw_dev), const_cast<float *>(dbw_dev));
+  });
 }
 
 int32_t bddmp_solver_round_primal(bddmp_solver *h, float *M_dev, int8_t *x_host, double *obj, int64_t *n_violated) {

@@ -87,6 +87,7 @@ struct ArenaLayout {
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
   size_t inst_row, inst_lb;
+  size_t cuts, cut_slots, cut_live, cut_arc, mu_in, dfw, dbw;
   size_t total;
 };
 
@@ -147,6 +148,21 @@ struct Plan {
   std::vector<int64_t> inst_var, inst_row, inst_inc;
   std::vector<double> inst_lb_const;
   std::vector<int32_t> inst_row32;    // inst_row as int32 for the device
+  // Sec. 6 split (n_cuts = 0 without one). A cut separates levels l and l+1 of a row whose variables
+  // lie in different intervals. The layer of level l (exit layer) then has no child layer: its arcs
+  // lead to a virtual child level with one slot per arc (2u + beta), holding the copy-arc duals
+  // mu_bar in the child-slot space; the layer of level l+1 (cut root) has no parent layer and
+  // takes its forward messages from the arc duals mu. Per cut, in canonical (row, level) order:
+  // cuts = {exit layer, root layer, first arc index, exit width | root width << 16},
+  // cut_slots = {exit own slot, exit child slot, root own slot, root child slot}, cut_live = index
+  // of its first live pair among all live pairs; cut_arc[arc] = the arc's child in the root level
+  // (kBot for an arc into BOT).
+  int32_t split_k = 0;
+  float split_gamma = 0.5f;
+  int64_t n_cuts = 0, n_arcs_cut = 0, n_copy = 0, n_cut_parts = 0;
+  std::vector<int32_t> var_interval;  // [n] interval of each variable (split only)
+  std::vector<int32_t> cuts, cut_slots, cut_live;
+  std::vector<uint16_t> cut_arc;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes
   uint32_t gsel = kDefaultGsel;

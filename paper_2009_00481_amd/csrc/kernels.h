@@ -48,6 +48,13 @@ struct Dev {
   int32_t hist_cap;
   uint32_t gsel;            // per tile width class, 4 bits: log2 of the lanes per general layer
                             // (0..6), or kFlat for the node-parallel tile path
+  // sub-BDD split (Sec. 6): cut tables (see Plan) and the copy-arc state per arc index; mu_bar of
+  // an arc sits in its exit layer's virtual child slot of mbc
+  const int4 *cuts, *cut_slots;
+  const int32_t *cut_live;
+  const uint16_t *cut_arc;
+  float *mu_in, *dfw, *dbw;
+  float gamma;
 };
 
 // One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).
@@ -72,6 +79,15 @@ hipError_t launch_set_counter(const Dev &D, long long value, hipStream_t s);
 hipError_t launch_instance_bounds(const Dev &D, int n_inst, hipStream_t s);
 hipError_t launch_residual(const Dev &D, int n, hipStream_t s);
 hipError_t launch_round(const Dev &D, int n, int m, hipStream_t s);
+
+// Sub-BDD split (split.hip): copy duals to zero; the forward and backward copy-arc updates of
+// Alg. "Parallel min-marginal averaging" (update = 0: only the cut roots' forward messages and the
+// bound partials, written at lbpart[part0 + block]); export / import of the copy state per live pair.
+hipError_t launch_copy_init(const Dev &D, int n_cuts, hipStream_t s);
+hipError_t launch_copy_fwd(const Dev &D, int n_cuts, hipStream_t s);
+hipError_t launch_copy_bwd(const Dev &D, int n_cuts, int update, int part0, hipStream_t s);
+hipError_t launch_copy_io(const Dev &D, int n_cuts, bool out, float *mu_bar, float *mu, float *dfw, float *dbw,
+                          hipStream_t s);
 
 // Smoothed variant (smooth.hip).
 struct SmoothArgs {

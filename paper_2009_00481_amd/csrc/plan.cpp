@@ -138,7 +138,8 @@ void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj,
 // addresses, that narrow records decode to the same arcs as the general array, and that tiles hold
 // whole variable segments and cover every layer once per pass. Returns an empty string when sound.
 std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, const std::vector<int32_t> &childw,
-                            const std::vector<int32_t> &level) {
+                            const std::vector<int32_t> &level, const std::vector<uint8_t> &exit_cut,
+                            const std::vector<uint8_t> &root_cut) {
   const int64_t I = P.I, S = P.S;
   if (int64_t(P.meta.size()) != I || int64_t(P.child.size()) != I || int64_t(P.parent.size()) != I ||
       int64_t(P.garcs.size()) != S)
@@ -152,21 +153,22 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     if (cs < 0 || cs + wc > P.Sc || (wc <= 2 && cs != 2 * L)) return "child slots";
     const int32_t cl = P.child[L];
     const uint32_t meta = P.meta[L];
-    if ((cl < 0) != (wc == 0)) return "child layer";
+    if (exit_cut[L] ? (cl >= 0 || wc != 2 * w) : ((cl < 0) != (wc == 0))) return "child layer";
     if (cl >= 0 && (cl >= I || P.canon_of[cl] != P.canon_of[L] + 1 || ownw[cl] != wc || P.parent[cl] != L))
       return "child layer";
     const int32_t pl = P.parent[L];
-    if ((pl < 0) != (level[L] == 0)) return "parent layer";
+    if ((pl < 0) != (level[L] == 0 || root_cut[L])) return "parent layer";
     if (pl >= 0 && (pl >= I || P.child[pl] != L || childw[pl] != w)) return "parent layer";
     for (int32_t u = 0; u < w; ++u) {
       const uint32_t a = P.garcs[size_t(os + u)];
       for (uint32_t ch : {a & 0xFFFFu, a >> 16}) {
         if (ch == kBot) continue;
         if (ch == kTop) {
-          if (cl >= 0) return "TOP before the last level";
+          if (cl >= 0 || exit_cut[L]) return "TOP before the last level";
           continue;
         }
-        if (cl < 0 || int32_t(ch) >= wc) return "child index outside the next level";
+        if ((cl < 0 && !exit_cut[L]) || int32_t(ch) >= wc) return "child index outside the next level";
+        if (exit_cut[L] && (ch >> 1) != uint32_t(u)) return "virtual child of a cut";
       }
     }
     const uint32_t w2 = (meta >> kMetaWidthShift) & 3u;
@@ -189,7 +191,7 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
       if (P.gnb[2 * size_t(L)] != (cl >= 0 ? P.own_slot[cl] : -1) || P.gnb[2 * size_t(L) + 1] != (pl >= 0 ? P.cslot[pl] : -1))
         return "neighbour slots";
       // the child level's in-arc lists hold exactly this level's arcs into it
-      if (wc > 0) {
+      if (wc > 0 && !exit_cut[L]) {
         const int64_t rb = g[3];
         if (rb < 0 || rb + wc >= int64_t(P.rbeg.size())) return "in-arc base";
         std::vector<int32_t> seen0(size_t(w), 0), seen1(size_t(w), 0);
@@ -276,6 +278,28 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     if (P.root_slot[j] >= S || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
   for (int32_t i = 0; i < P.n; ++i)
     if (P.var_nj[i] && (P.var_first[i] < 0 || P.var_first[i] + P.var_nj[i] > I)) return "var_first";
+  // cut tables: each cut names an exit layer and the root layer after it, with their slots and
+  // arc ranges inside the arrays
+  const int64_t nc = P.n_cuts;
+  if (int64_t(P.cuts.size()) != 4 * nc || int64_t(P.cut_slots.size()) != 4 * nc || int64_t(P.cut_live.size()) != nc ||
+      int64_t(P.cut_arc.size()) != P.n_arcs_cut)
+    return "cut arrays";
+  int64_t base = 0, live = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int32_t *k = &P.cuts[4 * size_t(c)], *sl = &P.cut_slots[4 * size_t(c)];
+    const int32_t Lx = k[0], Lr = k[1], wx = k[3] & 0xFFFF, wr = int32_t(uint32_t(k[3]) >> 16);
+    if (Lx < 0 || Lx >= I || Lr < 0 || Lr >= I || !exit_cut[Lx] || !root_cut[Lr] || P.canon_of[Lr] != P.canon_of[Lx] + 1)
+      return "cut layers";
+    if (k[2] != base || wx != ownw[Lx] || wr != ownw[Lr] || P.cut_live[size_t(c)] != live) return "cut record";
+    if (sl[0] != P.own_slot[Lx] || sl[1] != P.cslot[Lx] || sl[2] != P.own_slot[Lr] || sl[3] != P.cslot[Lr]) return "cut slots";
+    for (int32_t q = 0; q < 2 * wx; ++q) {
+      const uint32_t a = P.cut_arc[size_t(base + q)];
+      if (a != kBot && int32_t(a) >= wr) return "cut arc";
+      live += a != kBot;
+    }
+    base += 2 * wx;
+  }
+  if (live != P.n_copy) return "copy pairs";
   // instance row ranges: from 0 to m, non-decreasing (the bound kernel reads rows inside them)
   const size_t ni = P.inst_row32.size();
   if (ni < 2 || P.inst_row32[0] != 0 || P.inst_row32[ni - 1] != P.m || P.inst_lb_const.size() != ni - 1)
@@ -298,6 +322,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   P.hist_cap = opt.hist_cap > 0 ? opt.hist_cap : 4096;
   if (opt.tile_work < 0) return set_error(BDDMP_INVALID_ARG, "negative tile_work");
   if (opt.tile_work > 0) P.tile_work = opt.tile_work;
+  if (opt.n_intervals < 0) return set_error(BDDMP_INVALID_ARG, "negative n_intervals");
+  if (!(opt.split_gamma == 0.0f || (opt.split_gamma > 0.0f && opt.split_gamma <= 1.0f)))
+    return set_error(BDDMP_INVALID_ARG, "split_gamma must lie in (0, 1] (0: default)");
+  P.split_k = opt.n_intervals > 1 ? opt.n_intervals : 0;
+  P.split_gamma = opt.split_gamma > 0.0f ? opt.split_gamma : 0.5f;
   if (opt.tiling && !parse_groups(opt.tiling, P.gsel))
     return set_error(BDDMP_INVALID_ARG, "tiling must be four values, each 0 or a power of two up to 64, e.g. \"0,16,64,64\"");
   P.cost = p.cost;
@@ -416,7 +445,39 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     if (f0 && f1) return set_error(BDDMP_CONFLICT, "rows force variable " + std::to_string(i) + " to both 0 and 1");
   }
 
-  // dependency waves
+  // Sec. 6 split: per instance, its variables in processing order form split_k intervals of about
+  // equal node count (a variable counts the nodes of its levels over all its rows; the variable
+  // with c nodes before it among N lies in interval floor(split_k c / N)), and each row is cut
+  // between consecutive levels whose variables lie in different intervals
+  std::vector<uint8_t> cut_after(static_cast<size_t>(I), 0);
+  if (P.split_k) {
+    std::vector<int64_t> iv = p.inst_var.empty() ? std::vector<int64_t>{0, n} : p.inst_var;
+    std::vector<int32_t> inst_of(size_t(n), 0);
+    for (size_t x = 0; x + 1 < iv.size(); ++x)
+      for (int64_t i = iv[x]; i < iv[x + 1]; ++i) inst_of[size_t(i)] = int32_t(x);
+    std::vector<int64_t> vn(size_t(n), 0), tot(iv.size(), 0), cum(iv.size(), 0);
+    for (int64_t c = 0; c < I; ++c) {
+      const int32_t j = inc_row[c];
+      const Shape &sh = P.shapes[P.row_shape[j]];
+      const int32_t l = int32_t(c - P.canon_off[j]);
+      vn[P.inc_var[c]] += sh.first[l + 1] - sh.first[l];
+    }
+    for (int32_t i = 0; i < n; ++i) tot[inst_of[i]] += vn[i];
+    P.var_interval.assign(size_t(n), 0);
+    for (int32_t r = 0; r < n; ++r) {
+      const int32_t i = P.order[r], x = inst_of[i];
+      P.var_interval[i] = tot[x] ? int32_t(int64_t(P.split_k) * cum[x] / tot[x]) : 0;
+      cum[x] += vn[i];
+    }
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t c = P.canon_off[j]; c + 1 < P.canon_off[j + 1]; ++c)
+        if (P.var_interval[P.inc_var[c]] != P.var_interval[P.inc_var[c + 1]]) {
+          cut_after[c] = 1;
+          P.n_cuts++;
+        }
+  }
+
+  // dependency waves (a cut ends the chain: the levels after it start a sub-BDD of their own)
   P.wave_f.assign(size_t(n), 0);
   P.wave_b.assign(size_t(n), 0);
   for (int32_t r = 0; r < n; ++r) {
@@ -425,7 +486,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     int32_t t = 0;
     for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
       const int64_t c = ilist[q];
-      if (c > P.canon_off[inc_row[c]]) t = std::max(t, P.wave_f[P.inc_var[c - 1]]);
+      if (c > P.canon_off[inc_row[c]] && !cut_after[c - 1]) t = std::max(t, P.wave_f[P.inc_var[c - 1]]);
     }
     P.wave_f[i] = t + 1;
     P.Df = std::max(P.Df, t + 1);
@@ -436,7 +497,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     int32_t t = 0;
     for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
       const int64_t c = ilist[q];
-      if (c + 1 < P.canon_off[inc_row[c] + 1]) t = std::max(t, P.wave_b[P.inc_var[c + 1]]);
+      if (c + 1 < P.canon_off[inc_row[c] + 1] && !cut_after[c]) t = std::max(t, P.wave_b[P.inc_var[c + 1]]);
     }
     P.wave_b[i] = t + 1;
     P.Db = std::max(P.Db, t + 1);
@@ -468,7 +529,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       int64_t key = INT64_MAX;
       for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q) {
         const int32_t c = ilist[q];
-        if (c > P.canon_off[inc_row[c]]) key = std::min<int64_t>(key, P.layer_of[c - 1]);
+        if (c > P.canon_off[inc_row[c]] && !cut_after[c - 1]) key = std::min<int64_t>(key, P.layer_of[c - 1]);
       }
       keyed.emplace_back(key, P.rank[i]);
     }
@@ -494,6 +555,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   // has one node); wider levels follow after 2I, in layer order
   const size_t In0 = static_cast<size_t>(I);
   std::vector<int32_t> ownw(In0), childw(In0, 0), child_layer(In0, -1), level(In0);
+  std::vector<uint8_t> exit_cut(In0, 0), root_cut(In0, 0);
   for (int64_t Lq = 0; Lq < I; ++Lq) {
     const int32_t c = P.canon_of[Lq];
     const int32_t j = inc_row[c];
@@ -502,10 +564,18 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     level[Lq] = l;
     ownw[Lq] = sh.first[l + 1] - sh.first[l];
     if (l + 1 < sh.k) {
-      childw[Lq] = sh.first[l + 2] - sh.first[l + 1];
-      child_layer[Lq] = P.layer_of[c + 1];
+      if (cut_after[c]) {
+        exit_cut[Lq] = 1;
+        root_cut[P.layer_of[c + 1]] = 1;
+      } else {
+        childw[Lq] = sh.first[l + 2] - sh.first[l + 1];
+        child_layer[Lq] = P.layer_of[c + 1];
+      }
     }
   }
+  // an exit layer's virtual child level: one slot per arc
+  for (int64_t Lq = 0; Lq < I; ++Lq)
+    if (exit_cut[Lq]) childw[Lq] = 2 * ownw[Lq];
   // Forward messages of a layer's own level sit at its own slots; the backward messages of its
   // child level are kept in a second slot space at its child slots, written there by the child
   // layer's backward step. Both spaces put levels of at most 2 nodes at 2L, 2L+1.
@@ -547,14 +617,17 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     const int32_t l = level[Lq];
     const bool narrow = ownw[Lq] <= 2 && childw[Lq] <= 2;
     uint32_t meta = 0;
-    for (int32_t u = 0; u < ownw[Lq]; ++u) {
-      const int32_t lo = sh.lo[sh.first[l] + u], hi = sh.hi[sh.first[l] + u];
-      P.garcs[size_t(P.own_slot[Lq] + u)] = code16(lo) | (code16(hi) << 16);
-    }
+    // child of arc (u, beta): a node of the next level, or at a cut the arc's own virtual slot
+    auto arc_child = [&](int32_t u, int beta) -> int32_t {
+      const int32_t ch = beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u];
+      return (exit_cut[Lq] && ch >= 0) ? 2 * u + beta : ch;
+    };
+    for (int32_t u = 0; u < ownw[Lq]; ++u)
+      P.garcs[size_t(P.own_slot[Lq] + u)] = code16(arc_child(u, 0)) | (code16(arc_child(u, 1)) << 16);
     if (narrow) {
       for (int32_t u = 0; u < 2; ++u) {
-        const uint32_t lo = u < ownw[Lq] ? code2(sh.lo[sh.first[l] + u]) : kC2Bot;
-        const uint32_t hi = u < ownw[Lq] ? code2(sh.hi[sh.first[l] + u]) : kC2Bot;
+        const uint32_t lo = u < ownw[Lq] ? code2(arc_child(u, 0)) : kC2Bot;
+        const uint32_t hi = u < ownw[Lq] ? code2(arc_child(u, 1)) : kC2Bot;
         meta |= (lo | (hi << 2)) << (4 * u);
       }
       meta |= uint32_t(ownw[Lq]) << kMetaWidthShift;
@@ -584,7 +657,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       g[2] = ownw[Lq] | (childw[Lq] << 16);
       g[3] = -1;
       const bool narrow = ((P.meta[Lq] >> kMetaWidthShift) & 3u) != 0u;
-      if (narrow || childw[Lq] == 0) continue;
+      if (narrow || childw[Lq] == 0 || exit_cut[Lq]) continue;
       g[3] = int32_t(P.rbeg.size());
       lists.assign(size_t(childw[Lq]), {});
       for (int32_t u = 0; u < ownw[Lq]; ++u) {
@@ -613,6 +686,28 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.bdd_canon_off[j + 1] = int32_t(P.canon_off[j + 1]);
     if (P.canon_off[j + 1] > P.canon_off[j]) P.root_slot[j] = int32_t(P.own_slot[P.layer_of[P.canon_off[j]]]);
   }
+
+  // cut tables in canonical (row, level) order
+  for (int32_t j = 0; j < m; ++j)
+    for (int64_t c = P.canon_off[j]; c + 1 < P.canon_off[j + 1]; ++c) {
+      if (!cut_after[c]) continue;
+      const int32_t Lx = P.layer_of[c], Lr = P.layer_of[c + 1];
+      const Shape &sh = P.shapes[P.row_shape[j]];
+      const int32_t l = int32_t(c - P.canon_off[j]);
+      P.cuts.insert(P.cuts.end(), {Lx, Lr, int32_t(P.n_arcs_cut), ownw[Lx] | (ownw[Lr] << 16)});
+      P.cut_slots.insert(P.cut_slots.end(), {int32_t(P.own_slot[Lx]), int32_t(P.cslot[Lx]), int32_t(P.own_slot[Lr]),
+                                             int32_t(P.cslot[Lr])});
+      P.cut_live.push_back(int32_t(P.n_copy));
+      for (int32_t u = 0; u < ownw[Lx]; ++u)
+        for (int beta = 0; beta < 2; ++beta) {
+          const int32_t ch = beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u];
+          P.cut_arc.push_back(uint16_t(code16(ch)));
+          P.n_copy += ch >= 0;
+        }
+      P.n_arcs_cut += 2 * ownw[Lx];
+    }
+  if (P.n_arcs_cut >= INT32_MAX) return set_error(BDDMP_BDD_TOO_LARGE, "too many copy arcs");
+  P.n_cut_parts = (P.n_cuts + kTile - 1) / kTile;
 
   // forward tiles: positions are storage layers
   int64_t pos = 0;
@@ -747,13 +842,21 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.mbuf = take(4 * nn);
   A.xbuf = take(nn);
   A.part = take(8 * 2 * size_t(kLbBlocks));
-  A.lbpart = take(8 * size_t(P.n_lbpart + 1));
+  A.lbpart = take(8 * size_t(P.n_lbpart + P.n_cut_parts + 1));
   A.lb_hist = take(8 * size_t(P.hist_cap));
   A.scal = take(256);
   A.inst_row = take(4 * P.inst_row32.size());
   A.inst_lb = take(8 * P.inst_lb_const.size());
+  const size_t na = size_t(P.n_arcs_cut);
+  A.cuts = take(4 * P.cuts.size());
+  A.cut_slots = take(4 * P.cut_slots.size());
+  A.cut_live = take(4 * P.cut_live.size());
+  A.cut_arc = take(2 * na);
+  A.mu_in = take(4 * na);
+  A.dfw = take(4 * na);
+  A.dbw = take(4 * na);
   A.total = off;
-  const std::string bad = validate_layout(P, ownw, childw, level);
+  const std::string bad = validate_layout(P, ownw, childw, level, exit_cut, root_cut);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);
   return BDDMP_OK;
 }

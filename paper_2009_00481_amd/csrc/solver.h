@@ -20,6 +20,7 @@ int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out);
 int32_t solver_min_marginals(Solver &S, float *m0, float *m1);
 int32_t solver_get_lambda(Solver &S, float *lam);
 int32_t solver_set_lambda(Solver &S, const float *lam);
+int32_t solver_copy_duals(Solver &S, bool out, float *mu_bar, float *mu, float *dfw, float *dbw);
 int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj, int64_t *nviol);
 int32_t solver_set_graphs(Solver &S, int32_t enable);
 int32_t solver_set_groups(Solver &S, const int32_t *lanes);

@@ -107,21 +107,33 @@ int32_t enqueue_lb(Solver &S, std::vector<EventPair> *ev, hipStream_t st, int wh
   const Plan &P = *S.plan;
   Timer tm{ev};
   if (int32_t rc = tm.start(st, 2)) return rc;
-  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart), which, st), "bound reduction")) return rc;
+  if (int32_t rc = launched(launch_lb(S.D, int(P.n_lbpart + P.n_cut_parts), which, st), "bound reduction")) return rc;
   return tm.stop(st, 1);
+}
+
+// the cut roots' forward messages and the bound partials of the sub-BDDs they start (Sec. 6),
+// with (update) or without the backward copy-arc update
+int32_t enqueue_copy_bwd(Solver &S, int update, hipStream_t st) {
+  const Plan &P = *S.plan;
+  return launched(launch_copy_bwd(S.D, int(P.n_cuts), update, int(P.n_lbpart), st), "copy-arc update");
 }
 
 int32_t initial_sweep(Solver &S) {
   if (int32_t rc = run_pass(S, kBwd, kNoUpdate, nullptr, S.stream)) return rc;
+  if (int32_t rc = enqueue_copy_bwd(S, 0, S.stream)) return rc;
   if (int32_t rc = enqueue_lb(S, nullptr, S.stream)) return rc;
   S.n_hist++;
   return BDDMP_OK;
 }
 
-// enqueue one iteration (forward pass, backward pass, bound) on st
+// enqueue one iteration (forward pass, backward pass, bound) on st; with a split each pass is
+// followed by its copy-arc update (Alg. "Parallel min-marginal averaging")
 int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
+  const Plan &P = *S.plan;
   if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st)) return rc;
+  if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), st), "copy-arc update")) return rc;
   if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st)) return rc;
+  if (int32_t rc = enqueue_copy_bwd(S, 1, st)) return rc;
   return enqueue_lb(S, ev, st);
 }
 
@@ -215,6 +227,14 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.hist_cap = P.hist_cap;
   D.inst_row = reinterpret_cast<const int32_t *>(b + A.inst_row);
   D.inst_lb = reinterpret_cast<double *>(b + A.inst_lb);
+  D.cuts = reinterpret_cast<const int4 *>(b + A.cuts);
+  D.cut_slots = reinterpret_cast<const int4 *>(b + A.cut_slots);
+  D.cut_live = reinterpret_cast<const int32_t *>(b + A.cut_live);
+  D.cut_arc = reinterpret_cast<const uint16_t *>(b + A.cut_arc);
+  D.mu_in = reinterpret_cast<float *>(b + A.mu_in);
+  D.dfw = reinterpret_cast<float *>(b + A.dfw);
+  D.dbw = reinterpret_cast<float *>(b + A.dbw);
+  D.gamma = P.split_gamma;
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
     if (!nbytes) return hipSuccess;
@@ -244,6 +264,10 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.var_first, P.var_first.data(), 4 * P.var_first.size()),
       up(A.var_nj, P.var_nj.data(), 4 * P.var_nj.size()),
       up(A.inst_row, P.inst_row32.data(), 4 * P.inst_row32.size()),
+      up(A.cuts, P.cuts.data(), 4 * P.cuts.size()),
+      up(A.cut_slots, P.cut_slots.data(), 4 * P.cut_slots.size()),
+      up(A.cut_live, P.cut_live.data(), 4 * P.cut_live.size()),
+      up(A.cut_arc, P.cut_arc.data(), 2 * P.cut_arc.size()),
   };
   for (hipError_t e : errs)
     if (e != hipSuccess) {
@@ -269,6 +293,7 @@ int32_t solver_reset(Solver &S) {
   if (int32_t rc = launched(launch_fill(S.D.mbc, INFINITY, ncslots, S.stream), "fill")) return rc;
   if (int32_t rc = launched(launch_init_lambda(S.D, int(P.I), S.stream), "init_lambda")) return rc;
   if (int32_t rc = launched(launch_root_zero(S.D, P.m, S.stream), "root_zero")) return rc;
+  if (int32_t rc = launched(launch_copy_init(S.D, int(P.n_cuts), S.stream), "copy_init")) return rc;
   if (int32_t rc = launched(launch_set_counter(S.D, S.n_hist, S.stream), "set_counter")) return rc;
   if (int32_t rc = launched(launch_free_const(S.D, P.n, 1.0f, S.stream), "free_const")) return rc;
   S.iters = 0;
@@ -319,6 +344,7 @@ int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n) {
   const Plan &P = *S.plan;
   const int32_t n_inst = int32_t(P.inst_lb_const.size());
   if (S.costs_replaced) return set_error(BDDMP_BAD_STATE, "instance bounds use the plan's costs; costs were replaced");
+  if (P.n_cuts) return set_error(BDDMP_BAD_STATE, "instance bounds are not kept for a split plan");
   if (!lb_host || n != n_inst)
     return set_error(BDDMP_INVALID_ARG, "lb array must hold n_instances = " + std::to_string(n_inst) + " values");
   if (int32_t rc = launched(launch_instance_bounds(S.D, n_inst, S.stream), "instance_bounds")) return rc;
@@ -361,6 +387,15 @@ int32_t solver_set_lambda(Solver &S, const float *lam) {
   const Plan &P = *S.plan;
   if (int32_t rc = launched(launch_lambda_in(S.D, lam, int(P.I), S.stream), "lambda_in")) return rc;
   return initial_sweep(S);
+}
+
+int32_t solver_copy_duals(Solver &S, bool out, float *mu_bar, float *mu, float *dfw, float *dbw) {
+  const Plan &P = *S.plan;
+  if (!out && (!mu_bar || !mu || !dfw || !dbw) && P.n_copy)
+    return set_error(BDDMP_INVALID_ARG, "setting the copy state needs all four arrays");
+  if (int32_t rc = launched(launch_copy_io(S.D, int(P.n_cuts), out, mu_bar, mu, dfw, dbw, S.stream), "copy state"))
+    return rc;
+  return out ? BDDMP_OK : initial_sweep(S);
 }
 
 int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj, int64_t *nviol) {
@@ -538,6 +573,7 @@ int32_t smooth_check(Solver &S, float alpha, int32_t T, void *ws, size_t bytes, 
   if (T < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
   if (!P.fwd_big.empty() || !P.bwd_big.empty())
     return set_error(BDDMP_INVALID_ARG, "the smoothed passes take variables in at most 256 rows");
+  if (P.n_cuts) return set_error(BDDMP_INVALID_ARG, "the smoothed passes run on unsplit plans");
   w = smooth_layout(P, T, static_cast<char *>(ws));
   if (!ws || bytes < w.total) return set_error(BDDMP_INVALID_ARG, "workspace too small: need " + std::to_string(w.total));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(BDDMP_INVALID_ARG, "workspace not 256-byte aligned");

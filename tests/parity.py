@@ -10,12 +10,13 @@ from paper_2009_00481_amd import binding as B
 REL = 1e-4
 
 
-def run_gpu(ilp, iters: int, *, order_mode: int = 0, stages=None):
-    """Bind, iterate, read every output. stages: iterations after which the bound is read."""
+def run_gpu(ilp, iters: int, *, order_mode: int = 0, stages=None, split: int = 0, gamma: float = 0.0):
+    """Bind, iterate, read every output. stages: iterations after which the bound is read.
+    split / gamma: variable intervals and copy-arc step size of Sec. 6 (0: no split)."""
     import torch
 
     prob = B.Problem.from_ilp(ilp)
-    plan = B.Plan(prob, order_mode=order_mode, hist_cap=max(4096, iters + 8))
+    plan = B.Plan(prob, order_mode=order_mode, hist_cap=max(4096, iters + 8), n_intervals=split, split_gamma=gamma)
     s = B.Solver(plan)
     s.iterate(iters)
     lb, resid, any_lb = s.lower_bound()
@@ -29,8 +30,8 @@ def run_gpu(ilp, iters: int, *, order_mode: int = 0, stages=None):
                 M=M.cpu().numpy().astype(np.float64), x=x, obj=obj, nviol=nviol)
 
 
-def run_oracle(ilp, iters: int, precision: str = "f64"):
-    o = Oracle(ilp, precision=precision)
+def run_oracle(ilp, iters: int, precision: str = "f64", split: int = 0, gamma: float = 0.5):
+    o = Oracle(ilp, precision=precision, split=split, gamma=gamma)
     lb0 = o.init()
     tr = o.iterate(iters)
     m0, m1 = o.min_marginals()

@@ -1,0 +1,196 @@
+"""GPU parity of the sub-BDD split (Sec. 6, Alg. "Parallel min-marginal averaging").
+
+The wave schedule of a split plan runs the sub-BDDs of all intervals at once; each pass is followed
+by its copy-arc update. Bars as for the unsplit path: against the fp64 oracle every bound of the
+trace within relative 1e-4, multipliers, min-marginals and copy duals within 1e-4 of
+max(|ref|, S_j, 1) (S_j the row's sum of |lambda|); against the oracle's float mirror multipliers,
+min-marginals, total differences and copy duals bitwise equal, bounds to 1e-12 (fp64 sums in
+another order). A plan with one interval is the unsplit plan, bit for bit; a batched split plan
+gives each instance bitwise what its own split plan gives.
+"""
+import numpy as np
+import pytest
+
+from parity import REL, assert_incidence_close, assert_trace_close, incidence_scale, run_gpu, run_oracle
+from paper_2009_00481_amd import binding as B
+from paper_2009_00481_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "cfg1":
+        return I.config(1), 40
+    if name == "rand":
+        return I.random_ilp(40, 30, kmin=1, kmax=10, cmax=3, seed=2), 25
+    if name == "gm":
+        return I.graph_matching(300, 300, 10, 3000, seed=1), 20
+    if name == "track":
+        return I.tracking(400, seed=3), 20
+    if name == "tomo":
+        return I.tomography(8, seed=3, unary="normal"), 20
+    if name == "cfg5sub":
+        return I.config("5sub"), 20
+    raise ValueError(name)
+
+
+CASES = [("cfg1", 2, 0), ("cfg1", 5, 1), ("rand", 3, 0), ("gm", 4, 1), ("track", 3, 0), ("tomo", 4, 1),
+         ("tomo", 8, 0), ("cfg5sub", 3, 1)]
+
+
+def _ordered(ilp, plan):
+    o = plan.order()
+    return I.ILP(ilp.n, ilp.cost, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, o)
+
+
+def _copy_scale(ilp, cd, lam_ref):
+    rows = cd["row"]
+    return incidence_scale_rows(ilp, lam_ref)[rows]
+
+
+def incidence_scale_rows(ilp, lam_ref):
+    nz = np.asarray(ilp.coef) != 0
+    row_of_nnz = np.repeat(np.arange(ilp.m), np.diff(ilp.row_ptr))
+    lens = np.bincount(row_of_nnz[nz], minlength=ilp.m)
+    row_of = np.repeat(np.arange(ilp.m), lens)
+    s = np.zeros(ilp.m)
+    np.add.at(s, row_of, np.abs(lam_ref))
+    return s
+
+
+@pytest.mark.parametrize("name,K,order_mode", CASES)
+def test_split_parity_against_fp64_oracle(name, K, order_mode):
+    ilp, iters = _case(name)
+    print(f"[split fp64] {name} K={K} order={order_mode}", flush=True)
+    g = run_gpu(ilp, iters, order_mode=order_mode, split=K)
+    q = _ordered(ilp, g["plan"])
+    r = run_oracle(q, iters, "f64", split=K)
+    assert g["plan"].stats.n_cuts == r["o"].split_info()[1] > 0
+    assert_trace_close(g["hist"], r["hist"])
+    scale = incidence_scale(q, r["lam"])
+    assert_incidence_close(g["lam"], r["lam"], scale, what="lambda")
+    assert_incidence_close(g["m0"], r["m0"], scale, what="m0")
+    assert_incidence_close(g["m1"], r["m1"], scale, what="m1")
+    cd = r["o"].copy_duals()
+    mub, mu, _, _ = (t.cpu().numpy().astype(np.float64) for t in g["solver"].copy_duals())
+    cs = _copy_scale(q, cd, r["lam"])
+    assert_incidence_close(mub, cd["mu_bar"], cs, what="mu_bar")
+    assert_incidence_close(mu, cd["mu"], cs, what="mu")
+    # Prop. "correctness-parallel": monotone on the GPU too; copy duals feasible
+    h = g["hist"]
+    assert np.all(np.diff(h) >= -1e-6 * np.maximum(np.abs(h[1:]), 1.0))
+    assert np.all(mu + mub <= 1e-6 * np.maximum(cs, 1.0))
+
+
+@pytest.mark.parametrize("name,K,order_mode", CASES)
+def test_split_bitwise_against_fp32_mirror(name, K, order_mode):
+    ilp, iters = _case(name)
+    print(f"[split fp32] {name} K={K} order={order_mode}", flush=True)
+    g = run_gpu(ilp, iters, order_mode=order_mode, split=K)
+    q = _ordered(ilp, g["plan"])
+    r = run_oracle(q, iters, "f32", split=K)
+    assert np.array_equal(g["lam"], r["lam"]), np.max(np.abs(g["lam"] - r["lam"]))
+    assert np.array_equal(g["m0"], r["m0"])
+    assert np.array_equal(g["m1"], r["m1"])
+    assert np.array_equal(g["M"], r["M"])
+    assert np.array_equal(g["x"], r["x"])
+    cd = r["o"].copy_duals()
+    mub, mu, dfw, dbw = (t.cpu().numpy().astype(np.float64) for t in g["solver"].copy_duals())
+    assert np.array_equal(mub, cd["mu_bar"])
+    assert np.array_equal(mu, cd["mu"])
+    np.testing.assert_allclose(g["hist"], r["hist"], rtol=1e-12, atol=1e-9)
+
+
+def test_one_interval_is_the_unsplit_plan():
+    ilp, iters = _case("cfg1")
+    a = run_gpu(ilp, iters)
+    b = run_gpu(ilp, iters, split=1)
+    assert b["plan"].stats.n_cuts == 0
+    for k in ("lam", "m0", "m1", "hist"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batched_split_equals_each_instance():
+    import torch
+
+    ilps = [I.tomography(6 + (k % 3), seed=k, unary="normal") for k in range(3)] + \
+           [I.tracking(200 + 50 * k, seed=k) for k in range(3)]
+    K, iters = 3, 8
+    probs = [B.Problem.from_ilp(p) for p in ilps]
+    for om in (0, 1):
+        print(f"[split batched] order={om}", flush=True)
+        plan = B.Plan(probs, order_mode=om, n_intervals=K)
+        s = B.Solver(plan)
+        s.iterate(iters)
+        lam = s.get_lambda().cpu().numpy()
+        m0, m1 = (t.cpu().numpy() for t in s.min_marginals())
+        _, _, inc = plan.instances()
+        for k, p in enumerate(probs):
+            pk = B.Plan(p, order_mode=om, n_intervals=K)
+            sk = B.Solver(pk)
+            sk.iterate(iters)
+            a, b = int(inc[k]), int(inc[k + 1])
+            assert np.array_equal(lam[a:b], sk.get_lambda().cpu().numpy()), k
+            k0, k1 = (t.cpu().numpy() for t in sk.min_marginals())
+            assert np.array_equal(m0[a:b], k0) and np.array_equal(m1[a:b], k1), k
+        torch.cuda.synchronize()
+        assert plan.stats.waves_fwd <= B.Plan(probs, order_mode=om).stats.waves_fwd
+
+
+def test_checkpoint_resume_and_graph_replay():
+    import torch
+
+    ilp, _ = _case("tomo")
+    plan = B.Plan(B.Problem.from_ilp(ilp), order_mode=1, n_intervals=4)
+    a = B.Solver(plan)
+    a.iterate(5)
+    lam = a.get_lambda().clone()
+    cdu = [t.clone() for t in a.copy_duals()]
+    a.iterate(5)
+    b = B.Solver(plan)
+    b.set_copy_duals(*cdu)
+    b.set_lambda(lam)
+    b.iterate(5)
+    c = B.Solver(plan)
+    c.set_graphs(False)
+    c.iterate(10)
+    torch.cuda.synchronize()
+    for x in (b, c):
+        assert np.array_equal(a.get_lambda().cpu().numpy(), x.get_lambda().cpu().numpy())
+        for u, v in zip(a.copy_duals(), x.copy_duals()):
+            assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())
+        assert a.lb_history(1)[0] == x.lb_history(1)[0]
+
+
+def test_split_errors():
+    import torch
+
+    plan = B.Plan(B.Problem.from_ilp(I.config(1)), n_intervals=3)
+    s = B.Solver(plan)
+    with pytest.raises(B.BddmpError) as e:
+        s.instance_bounds()
+    assert e.value.code == -7
+    nb = B.bddmp_smooth_workspace_bytes(plan.h, 2)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BddmpError) as e:
+        B.bddmp_solver_smooth_run(s.h, 1.0, 2, ws, nb)
+    assert e.value.code == -1
+
+
+def test_full_size_split_properties():
+    """The 256x256x8 Potts workload with 8 intervals: 30 iterations, bound finite, non-decreasing,
+    below the unsplit bound's ceiling (any lambda bound of the unsplit plan is not needed: the
+    split bound is a valid bound, so it stays below the rounded primal's objective when feasible)."""
+    import torch
+
+    ilp = I.config(2)
+    plan = B.Plan(B.Problem.from_ilp(ilp), n_intervals=8, hist_cap=64)
+    print(f"[split full] cuts={plan.stats.n_cuts} waves={plan.stats.waves_fwd}", flush=True)
+    s = B.Solver(plan)
+    s.iterate(30)
+    h = s.lb_history(31)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(h))
+    assert np.all(np.diff(h) >= -1e-6 * np.abs(h[1:]))
+    mub, mu, _, _ = s.copy_duals()
+    assert bool(torch.all(mu + mub <= 1e-3))

@@ -144,6 +144,64 @@ def batched_vs_plain(args, B, I, torch):
             "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s}}
 
 
+def split_vs_plain(args, B, I, torch):
+    """Sec. 6 sub-BDD split on the batched workload: each instance's variables cut into K intervals
+    of about equal node count, fewer dependency waves per pass, copy-arc updates between the passes.
+    Per K: waves, time per iteration, and the iterations and time until the bound reaches the one the
+    unsplit schedule has after --split-iters iterations (the split converges per iteration more
+    slowly, each iteration is shorter)."""
+    import numpy as np
+
+    n = args.batch_instances
+    probs = [B.Problem.from_ilp(q) for q in I.batch_config(n)]
+    T = args.split_iters
+    ks = [int(k) for k in args.split_k.split(",") if k]
+
+    def run(K, iters):
+        t = time.perf_counter()
+        plan = B.Plan(probs, hist_cap=max(4096, iters + 8), n_intervals=K)
+        plan_s = time.perf_counter() - t
+        st = plan.stats
+        s = B.Solver(plan)
+        s.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(10)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 10
+        s.reset()
+        s.iterate(iters)
+        hist = s.lb_history(iters + 1)
+        torch.cuda.synchronize()
+        del s
+        torch.cuda.empty_cache()
+        return st, ms, hist, plan_s
+
+    marks = [t for t in (1, 5, 10, 20, 50, 100, 200) if t <= T]
+    st0, ms0, h0, _ = run(0, T)
+    # target: within 1e-4 (relative) of the unsplit schedule's bound after T iterations
+    target = float(h0[-1]) - 1e-4 * max(abs(float(h0[-1])), 1.0)
+    it0 = int(np.nonzero(h0 >= target)[0][0])
+    out = {"workload": f"batch{n} (as batched_vs_plain)", "reference_iters": T,
+           "reference_bound": float(h0[-1]), "target": target,
+           "plain": {"waves_per_pass": [int(st0.waves_fwd), int(st0.waves_bwd)], "ms_per_iter": ms0,
+                     "iters_to_target": it0, "ms_to_target": it0 * ms0,
+                     "bound_at": {t: float(h0[t]) for t in marks}}, "split": []}
+    log(f"[bench] split: plain {st0.waves_fwd} waves, {ms0:.2f} ms/iter, bound {h0[-1]:.6g} after {T}, "
+        f"target at {it0} iterations")
+    for K in ks:
+        st, ms, h, plan_s = run(K, args.split_max_iters)
+        hit = np.nonzero(h >= target)[0]
+        it = int(hit[0]) if hit.size else None
+        rec = {"n_intervals": K, "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
+               "n_cuts": int(st.n_cuts), "n_copy_pairs": int(st.n_copy_pairs), "ms_per_iter": ms,
+               "bound_at": {t: float(h[t]) for t in marks}, "iters_to_target": it,
+               "ms_to_target": None if it is None else it * ms, "plan_s": plan_s}
+        out["split"].append(rec)
+        log(f"[bench] split K={K}: {st.waves_fwd} waves, {ms:.2f} ms/iter, target at {it} iterations")
+    return out
+
+
 def smoothed_vs_plain(args, B, I, torch):
     """The differentiable form: smoothed DBCA forward (T iterations with per-iteration multiplier
     checkpoints) and its adjoint (d LB_alpha / d c), against plain min-plus iterations on the same
@@ -196,7 +254,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-smoothed", action="store_true", help="skip the smoothed-vs-plain comparison")
     ap.add_argument("--smooth-iters", type=int, default=50)
-    ap.add_argument("--only", choices=["batched", "smoothed"], default=None,
+    ap.add_argument("--no-split", action="store_true", help="skip the split-vs-plain comparison")
+    ap.add_argument("--split-k", default="4,16", help="interval counts of the split comparison")
+    ap.add_argument("--split-iters", type=int, default=100)
+    ap.add_argument("--split-max-iters", type=int, default=300)
+    ap.add_argument("--only", choices=["batched", "smoothed", "split"], default=None,
                     help="run only this comparison and print its object (profiling)")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=20)
@@ -228,7 +290,7 @@ def main():
 
     if args.only:
         torch.cuda.set_device(0)
-        fn = batched_vs_plain if args.only == "batched" else smoothed_vs_plain
+        fn = {"batched": batched_vs_plain, "smoothed": smoothed_vs_plain, "split": split_vs_plain}[args.only]
         print(json.dumps({args.only: fn(args, B, I, torch)}), flush=True)
         return
 
@@ -357,6 +419,11 @@ def main():
         batched = batched_vs_plain(args, B, I, torch)
         log(f"[bench] batched vs plain: {batched['batched_ms_per_iter']:.2f} vs {batched['plain_ms_per_iter']:.1f} ms/iter")
 
+    split = None
+    if not args.no_split:
+        torch.cuda.empty_cache()
+        split = split_vs_plain(args, B, I, torch)
+
     rec = {
         "metric": METRIC, "value": value, "unit": "arc-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -372,6 +439,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "batched_vs_plain": batched,
         "smoothed_vs_plain": smoothed,
+        "split_vs_plain": split,
     }
     print(json.dumps(rec), flush=True)
 

@@ -16,6 +16,7 @@ constexpr int32_t kMaxWidth = 0x7FFF;   // widest level the 16-bit child codes c
 constexpr int kTile = 256;              // layers per workgroup of the wave kernels
 constexpr int kBigMax = 4096;           // max rows of one variable (J_i) a wave kernel handles
 constexpr int kLbBlocks = 1024;         // fixed partial count of the deterministic fp64 reductions
+constexpr int kCutsPerBlock = 4;        // wide cuts per workgroup of the copy-arc kernels (one wavefront each)
 
 // 2-bit child codes of a narrow layer (both its level and the next have at most 2 nodes)
 constexpr uint32_t kC2Bot = 2u, kC2Top = 3u;
@@ -87,7 +88,7 @@ struct ArenaLayout {
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
   size_t inst_row, inst_lb;
-  size_t cuts, cut_slots, cut_live, cut_arc, mu_in, dfw, dbw;
+  size_t cuts, cut_slots, cut_live, cut_rb, cut_arc, mu_in, dfw, dbw;
   size_t total;
 };
 
@@ -155,13 +156,15 @@ struct Plan {
   // takes its forward messages from the arc duals mu. Per cut, in canonical (row, level) order:
   // cuts = {exit layer, root layer, first arc index, exit width | root width << 16},
   // cut_slots = {exit own slot, exit child slot, root own slot, root child slot}, cut_live = index
-  // of its first live pair among all live pairs; cut_arc[arc] = the arc's child in the root level
-  // (kBot for an arc into BOT).
+  // of its first live pair among all live pairs (canonical order); cut_arc[arc] = the arc's child in
+  // the root level (kBot for an arc into BOT), arcs numbered in canonical cut order. Records list
+  // the n_cut_narrow narrow cuts (both levels at most 2 nodes) first, then the wide ones; cut_rb =
+  // base of a wide cut's root-level in-arc lists in rbeg / rin (-1 for narrow cuts).
   int32_t split_k = 0;
   float split_gamma = 0.5f;
-  int64_t n_cuts = 0, n_arcs_cut = 0, n_copy = 0, n_cut_parts = 0;
+  int64_t n_cuts = 0, n_cut_narrow = 0, n_arcs_cut = 0, n_copy = 0, n_cut_parts = 0;
   std::vector<int32_t> var_interval;  // [n] interval of each variable (split only)
-  std::vector<int32_t> cuts, cut_slots, cut_live;
+  std::vector<int32_t> cuts, cut_slots, cut_live, cut_rb;
   std::vector<uint16_t> cut_arc;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes

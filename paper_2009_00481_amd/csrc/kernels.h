@@ -51,7 +51,7 @@ struct Dev {
   // sub-BDD split (Sec. 6): cut tables (see Plan) and the copy-arc state per arc index; mu_bar of
   // an arc sits in its exit layer's virtual child slot of mbc
   const int4 *cuts, *cut_slots;
-  const int32_t *cut_live;
+  const int32_t *cut_live, *cut_rb;
   const uint16_t *cut_arc;
   float *mu_in, *dfw, *dbw;
   float gamma;
@@ -84,8 +84,9 @@ hipError_t launch_round(const Dev &D, int n, int m, hipStream_t s);
 // Alg. "Parallel min-marginal averaging" (update = 0: only the cut roots' forward messages and the
 // bound partials, written at lbpart[part0 + block]); export / import of the copy state per live pair.
 hipError_t launch_copy_init(const Dev &D, int n_cuts, hipStream_t s);
-hipError_t launch_copy_fwd(const Dev &D, int n_cuts, hipStream_t s);
-hipError_t launch_copy_bwd(const Dev &D, int n_cuts, int update, int part0, hipStream_t s);
+// n_narrow: the leading narrow cuts (one lane each); the others run one wavefront each.
+hipError_t launch_copy_fwd(const Dev &D, int n_cuts, int n_narrow, hipStream_t s);
+hipError_t launch_copy_bwd(const Dev &D, int n_cuts, int n_narrow, int update, int part0, hipStream_t s);
 hipError_t launch_copy_io(const Dev &D, int n_cuts, bool out, float *mu_bar, float *mu, float *dfw, float *dbw,
                           hipStream_t s);
 

@@ -282,24 +282,54 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
   // arc ranges inside the arrays
   const int64_t nc = P.n_cuts;
   if (int64_t(P.cuts.size()) != 4 * nc || int64_t(P.cut_slots.size()) != 4 * nc || int64_t(P.cut_live.size()) != nc ||
-      int64_t(P.cut_arc.size()) != P.n_arcs_cut)
+      int64_t(P.cut_rb.size()) != nc || int64_t(P.cut_arc.size()) != P.n_arcs_cut || P.n_cut_narrow > nc)
     return "cut arrays";
-  int64_t base = 0, live = 0;
+  std::vector<uint8_t> arc_seen(size_t(P.n_arcs_cut), 0), live_seen(size_t(P.n_copy), 0);
   for (int64_t c = 0; c < nc; ++c) {
     const int32_t *k = &P.cuts[4 * size_t(c)], *sl = &P.cut_slots[4 * size_t(c)];
     const int32_t Lx = k[0], Lr = k[1], wx = k[3] & 0xFFFF, wr = int32_t(uint32_t(k[3]) >> 16);
     if (Lx < 0 || Lx >= I || Lr < 0 || Lr >= I || !exit_cut[Lx] || !root_cut[Lr] || P.canon_of[Lr] != P.canon_of[Lx] + 1)
       return "cut layers";
-    if (k[2] != base || wx != ownw[Lx] || wr != ownw[Lr] || P.cut_live[size_t(c)] != live) return "cut record";
+    if (wx != ownw[Lx] || wr != ownw[Lr] || k[2] < 0 || k[2] + 2 * wx > P.n_arcs_cut) return "cut record";
+    if ((c < P.n_cut_narrow) != (wx <= 2 && wr <= 2)) return "cut class";
     if (sl[0] != P.own_slot[Lx] || sl[1] != P.cslot[Lx] || sl[2] != P.own_slot[Lr] || sl[3] != P.cslot[Lr]) return "cut slots";
+    int64_t live = P.cut_live[size_t(c)];
+    std::vector<int32_t> into(size_t(wr), 0);
     for (int32_t q = 0; q < 2 * wx; ++q) {
-      const uint32_t a = P.cut_arc[size_t(base + q)];
-      if (a != kBot && int32_t(a) >= wr) return "cut arc";
-      live += a != kBot;
+      if (arc_seen[size_t(k[2] + q)]++) return "cut arcs overlap";
+      const uint32_t a = P.cut_arc[size_t(k[2] + q)];
+      if (a == kBot) continue;
+      if (int32_t(a) >= wr) return "cut arc";
+      into[a]++;
+      if (live < 0 || live >= P.n_copy || live_seen[size_t(live)]++) return "copy pairs";
+      ++live;
     }
-    base += 2 * wx;
+    const int32_t rb = P.cut_rb[size_t(c)];
+    if (c < P.n_cut_narrow) {
+      if (rb != -1) return "cut in-arcs";
+      continue;
+    }
+    // the root level's in-arc lists hold exactly the cut's live arcs into each node
+    if (rb < 0 || int64_t(rb) + wr >= int64_t(P.rbeg.size()) || P.rin.size() != P.rbeg.size()) return "cut in-arcs";
+    for (int32_t v = 0; v < wr; ++v) {
+      const int64_t b0 = P.rbeg[size_t(rb + v)], b1 = P.rbeg[size_t(rb + v + 1)];
+      if (b0 < 0 || b1 < b0 || b1 > int64_t(P.rarc.size()) || b1 - b0 != into[v]) return "cut in-arcs";
+      const uint32_t pk = P.rin[size_t(rb + v)];
+      if (b1 - b0 > 2 || b1 == b0 ? pk != kManyInArcs
+                                  : ((pk & 0xFFFFu) != P.rarc[size_t(b0)] ||
+                                     (pk >> 16) != (b1 - b0 > 1 ? uint32_t(P.rarc[size_t(b0 + 1)]) : kNoArc16)))
+        return "cut packed in-arcs";
+      for (int64_t q = b0; q < b1; ++q) {
+        const uint32_t a = P.rarc[size_t(q)];
+        const int32_t u = int32_t(a & (kInArcHi - 1u));
+        if (u >= wx || P.cut_arc[size_t(k[2] + 2 * u + ((a & kInArcHi) ? 1 : 0))] != uint32_t(v)) return "cut in-arc target";
+      }
+    }
   }
-  if (live != P.n_copy) return "copy pairs";
+  for (uint8_t f : arc_seen)
+    if (!f) return "cut arcs not covered";
+  for (uint8_t f : live_seen)
+    if (!f) return "copy pairs not covered";
   // instance row ranges: from 0 to m, non-decreasing (the bound kernel reads rows inside them)
   const size_t ni = P.inst_row32.size();
   if (ni < 2 || P.inst_row32[0] != 0 || P.inst_row32[ni - 1] != P.m || P.inst_lb_const.size() != ni - 1)
@@ -687,27 +717,59 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     if (P.canon_off[j + 1] > P.canon_off[j]) P.root_slot[j] = int32_t(P.own_slot[P.layer_of[P.canon_off[j]]]);
   }
 
-  // cut tables in canonical (row, level) order
-  for (int32_t j = 0; j < m; ++j)
-    for (int64_t c = P.canon_off[j]; c + 1 < P.canon_off[j + 1]; ++c) {
-      if (!cut_after[c]) continue;
-      const int32_t Lx = P.layer_of[c], Lr = P.layer_of[c + 1];
-      const Shape &sh = P.shapes[P.row_shape[j]];
-      const int32_t l = int32_t(c - P.canon_off[j]);
-      P.cuts.insert(P.cuts.end(), {Lx, Lr, int32_t(P.n_arcs_cut), ownw[Lx] | (ownw[Lr] << 16)});
-      P.cut_slots.insert(P.cut_slots.end(), {int32_t(P.own_slot[Lx]), int32_t(P.cslot[Lx]), int32_t(P.own_slot[Lr]),
-                                             int32_t(P.cslot[Lr])});
-      P.cut_live.push_back(int32_t(P.n_copy));
-      for (int32_t u = 0; u < ownw[Lx]; ++u)
-        for (int beta = 0; beta < 2; ++beta) {
-          const int32_t ch = beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u];
-          P.cut_arc.push_back(uint16_t(code16(ch)));
-          P.n_copy += ch >= 0;
+  // cut tables: arcs and live pairs numbered in canonical (row, level) order; the cut records list
+  // the narrow cuts (both levels at most 2 nodes, one lane each) first, then the wide ones (one
+  // wavefront each, with in-arc lists of the root level for its forward messages)
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t base = 0, live = 0;
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t c = P.canon_off[j]; c + 1 < P.canon_off[j + 1]; ++c) {
+        if (!cut_after[c]) continue;
+        const int32_t Lx = P.layer_of[c], Lr = P.layer_of[c + 1];
+        const Shape &sh = P.shapes[P.row_shape[j]];
+        const int32_t l = int32_t(c - P.canon_off[j]);
+        const bool narrow = ownw[Lx] <= 2 && ownw[Lr] <= 2;
+        int32_t nlive = 0;
+        for (int32_t u = 0; u < ownw[Lx]; ++u)
+          nlive += (sh.lo[sh.first[l] + u] >= 0) + (sh.hi[sh.first[l] + u] >= 0);
+        if (narrow == (pass == 0)) {
+          int32_t rb = -1;
+          if (!narrow) {
+            rb = int32_t(P.rbeg.size());
+            std::vector<std::vector<uint16_t>> lists(static_cast<size_t>(ownw[Lr]));
+            for (int32_t u = 0; u < ownw[Lx]; ++u) {
+              if (sh.lo[sh.first[l] + u] >= 0) lists[sh.lo[sh.first[l] + u]].push_back(uint16_t(u));
+              if (sh.hi[sh.first[l] + u] >= 0) lists[sh.hi[sh.first[l] + u]].push_back(uint16_t(uint32_t(u) | kInArcHi));
+            }
+            for (const auto &li : lists) {
+              P.rbeg.push_back(int32_t(P.rarc.size()));
+              P.rarc.insert(P.rarc.end(), li.begin(), li.end());
+              P.rin.push_back(li.size() > 2 ? kManyInArcs
+                                            : (li.size() > 0 ? li[0] : kNoArc16) | ((li.size() > 1 ? li[1] : kNoArc16) << 16));
+            }
+            P.rbeg.push_back(int32_t(P.rarc.size()));
+            P.rin.push_back(kManyInArcs);
+          }
+          P.cuts.insert(P.cuts.end(), {Lx, Lr, int32_t(base), ownw[Lx] | (ownw[Lr] << 16)});
+          P.cut_slots.insert(P.cut_slots.end(), {int32_t(P.own_slot[Lx]), int32_t(P.cslot[Lx]),
+                                                 int32_t(P.own_slot[Lr]), int32_t(P.cslot[Lr])});
+          P.cut_live.push_back(int32_t(live));
+          P.cut_rb.push_back(rb);
+          P.n_cut_narrow += narrow;
         }
-      P.n_arcs_cut += 2 * ownw[Lx];
-    }
-  if (P.n_arcs_cut >= INT32_MAX) return set_error(BDDMP_BDD_TOO_LARGE, "too many copy arcs");
-  P.n_cut_parts = (P.n_cuts + kTile - 1) / kTile;
+        if (pass == 0) {
+          for (int32_t u = 0; u < ownw[Lx]; ++u)
+            for (int beta = 0; beta < 2; ++beta)
+              P.cut_arc.push_back(uint16_t(code16(beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u])));
+          P.n_arcs_cut += 2 * ownw[Lx];
+          P.n_copy += nlive;
+        }
+        base += 2 * ownw[Lx];
+        live += nlive;
+      }
+  }
+  if (P.n_arcs_cut >= INT32_MAX || P.rarc.size() >= size_t(INT32_MAX)) return set_error(BDDMP_BDD_TOO_LARGE, "too many copy arcs");
+  P.n_cut_parts = (P.n_cut_narrow + kTile - 1) / kTile + (P.n_cuts - P.n_cut_narrow + kCutsPerBlock - 1) / kCutsPerBlock;
 
   // forward tiles: positions are storage layers
   int64_t pos = 0;
@@ -851,6 +913,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.cuts = take(4 * P.cuts.size());
   A.cut_slots = take(4 * P.cut_slots.size());
   A.cut_live = take(4 * P.cut_live.size());
+  A.cut_rb = take(4 * P.cut_rb.size());
   A.cut_arc = take(2 * na);
   A.mu_in = take(4 * na);
   A.dfw = take(4 * na);

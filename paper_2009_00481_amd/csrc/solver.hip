@@ -115,7 +115,8 @@ int32_t enqueue_lb(Solver &S, std::vector<EventPair> *ev, hipStream_t st, int wh
 // with (update) or without the backward copy-arc update
 int32_t enqueue_copy_bwd(Solver &S, int update, hipStream_t st) {
   const Plan &P = *S.plan;
-  return launched(launch_copy_bwd(S.D, int(P.n_cuts), update, int(P.n_lbpart), st), "copy-arc update");
+  return launched(launch_copy_bwd(S.D, int(P.n_cuts), int(P.n_cut_narrow), update, int(P.n_lbpart), st),
+                  "copy-arc update");
 }
 
 int32_t initial_sweep(Solver &S) {
@@ -131,7 +132,7 @@ int32_t initial_sweep(Solver &S) {
 int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
   const Plan &P = *S.plan;
   if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st)) return rc;
-  if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), st), "copy-arc update")) return rc;
+  if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), int(P.n_cut_narrow), st), "copy-arc update")) return rc;
   if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st)) return rc;
   if (int32_t rc = enqueue_copy_bwd(S, 1, st)) return rc;
   return enqueue_lb(S, ev, st);
@@ -230,6 +231,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.cuts = reinterpret_cast<const int4 *>(b + A.cuts);
   D.cut_slots = reinterpret_cast<const int4 *>(b + A.cut_slots);
   D.cut_live = reinterpret_cast<const int32_t *>(b + A.cut_live);
+  D.cut_rb = reinterpret_cast<const int32_t *>(b + A.cut_rb);
   D.cut_arc = reinterpret_cast<const uint16_t *>(b + A.cut_arc);
   D.mu_in = reinterpret_cast<float *>(b + A.mu_in);
   D.dfw = reinterpret_cast<float *>(b + A.dfw);
@@ -267,6 +269,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.cuts, P.cuts.data(), 4 * P.cuts.size()),
       up(A.cut_slots, P.cut_slots.data(), 4 * P.cut_slots.size()),
       up(A.cut_live, P.cut_live.data(), 4 * P.cut_live.size()),
+      up(A.cut_rb, P.cut_rb.data(), 4 * P.cut_rb.size()),
       up(A.cut_arc, P.cut_arc.data(), 2 * P.cut_arc.size()),
   };
   for (hipError_t e : errs)

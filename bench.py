@@ -76,15 +76,24 @@ def committed_traffic(workload: str):
     return None
 
 
+_BATCH = {}
+
+
+def batch_instances(I, n):
+    """The batched workload's instances, generated once per run (seconds of host work)."""
+    if n not in _BATCH:
+        t = time.perf_counter()
+        _BATCH[n] = (I.batch_config(n), time.perf_counter() - t)
+    return _BATCH[n]
+
+
 def batched_vs_plain(args, B, I, torch):
     """The batched workload (tomography and tracking instances of uneven size) solved in one
     schedule against the same instances solved one after another through their own plans."""
     import numpy as np
 
     n = args.batch_instances
-    t = time.perf_counter()
-    insts = I.batch_config(n)
-    gen_s = time.perf_counter() - t
+    insts, gen_s = batch_instances(I, n)
     probs = [B.Problem.from_ilp(q) for q in insts]
     t = time.perf_counter()
     bp = B.Plan(probs)
@@ -153,7 +162,7 @@ def split_vs_plain(args, B, I, torch):
     import numpy as np
 
     n = args.batch_instances
-    probs = [B.Problem.from_ilp(q) for q in I.batch_config(n)]
+    probs = [B.Problem.from_ilp(q) for q in batch_instances(I, n)[0]]
     T = args.split_iters
     ks = [int(k) for k in args.split_k.split(",") if k]
 
@@ -255,7 +264,7 @@ def main():
     ap.add_argument("--no-smoothed", action="store_true", help="skip the smoothed-vs-plain comparison")
     ap.add_argument("--smooth-iters", type=int, default=50)
     ap.add_argument("--no-split", action="store_true", help="skip the split-vs-plain comparison")
-    ap.add_argument("--split-k", default="4,16", help="interval counts of the split comparison")
+    ap.add_argument("--split-k", default="4", help="interval counts of the split comparison")
     ap.add_argument("--split-iters", type=int, default=100)
     ap.add_argument("--split-max-iters", type=int, default=300)
     ap.add_argument("--only", choices=["batched", "smoothed", "split"], default=None,

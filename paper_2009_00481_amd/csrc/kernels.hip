@@ -157,8 +157,7 @@ __device__ __forceinline__ float float_of(unsigned u) {
 // step"): the minimum over its in-arcs of (source forward message + lam on a 1-arc). fu_of(u)
 // gives the forward message of this level's node u.
 template <class F>
-__device__ __forceinline__ float pull_min(const Dev &D, int rb, int v, float lam, F fu_of) {
-  const uint32_t pk = D.rin[rb + v];
+__device__ __forceinline__ float pull_min_pk(const Dev &D, uint32_t pk, int rb, int v, float lam, F fu_of) {
   if (pk != kManyInArcs) {
     const uint32_t a0 = pk & 0xFFFFu, a1 = pk >> 16;
     const float f0 = fu_of(int(a0 & (kInArcHi - 1u)));
@@ -177,6 +176,10 @@ __device__ __forceinline__ float pull_min(const Dev &D, int rb, int v, float lam
     val = fminf(val, (a & kInArcHi) ? fu + lam : fu);
   }
   return val;
+}
+template <class F>
+__device__ __forceinline__ float pull_min(const Dev &D, int rb, int v, float lam, F fu_of) {
+  return pull_min_pk(D, D.rin[rb + v], rb, v, lam, fu_of);
 }
 
 // Group path: one general layer per group of G lanes (G a power of two up to 64; groups are
@@ -284,6 +287,10 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   uint32_t ar[NARROW_ONLY ? 1 : kFlatR];
   float fr[NARROW_ONLY ? 1 : kFlatR];
   int kr[NARROW_ONLY ? 1 : kFlatR];
+  // flat path, forward: layer of each staged next-level node and its packed in-arcs, loaded with
+  // the node's backward message so that the pull needs no further round trip
+  int kc[NARROW_ONLY ? 1 : kFlatR];
+  uint32_t pkc[NARROW_ONLY ? 1 : kFlatR];
   if constexpr (!NARROW_ONLY) {
     GenTile &T = s_g;
     // compact index of the tile's general layers (ballot prefix per wavefront), and exclusive
@@ -361,10 +368,14 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         const int t = s + r * kTile;
+        kc[r] = -1;
+        pkc[r] = kManyInArcs;
         if (r * kTile < TC && t < TC) {
           int k = s_ckc[t >> 6];
           while (k + 1 < ngen && T.co[k + 1] <= t) ++k;
+          kc[r] = k;
           s_cb[t] = D.mbc[T.cs[k] + (t - T.co[k])];
+          if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];
         }
       }
       __syncthreads();
@@ -454,14 +465,12 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         // "Forward BDD update step"), reading this level's forward messages from LDS
 #pragma unroll
         for (int r = 0; r < kFlatR; ++r) {
-          const int t = s + r * kTile;
-          if (r * kTile < TC && t < TC) {
-            int k = s_ckc[t >> 6];
-            while (k + 1 < ngen && T.co[k + 1] <= t) ++k;
+          const int k = kc[r];
+          if (k >= 0) {
             const int osc = T.osc[k];
             if (osc >= 0) {
-              const int v = t - T.co[k], f0 = T.wo[k];
-              D.mf[osc + v] = pull_min(D, T.rb[k], v, T.lam[k], [&](int u) { return s_fu[f0 + u]; });
+              const int v = s + r * kTile - T.co[k], f0 = T.wo[k];
+              D.mf[osc + v] = pull_min_pk(D, pkc[r], T.rb[k], v, T.lam[k], [&](int u) { return s_fu[f0 + u]; });
             }
           }
         }

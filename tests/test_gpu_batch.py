@@ -97,3 +97,45 @@ def test_instance_bound_of_a_single_plan_is_the_bound():
     with pytest.raises(B.BddmpError) as e:
         B.bddmp_solver_instance_bounds(s.h, 2)
     assert e.value.code == -1
+
+
+def test_full_size_batched_workload():
+    """The 256-instance batched workload at its full size, in the launch configuration the benchmark
+    times (graph replay): bound finite and non-decreasing, the instance bounds add up to it, sampled
+    instances bitwise equal to their own plans, and the smallest tomography instance against the fp64
+    oracle."""
+    import torch
+
+    insts = I.batch_config(256)
+    T = 8
+    bp = B.Plan([B.Problem.from_ilp(q) for q in insts])
+    print(f"[batch full] nodes={bp.stats.n_nodes} waves={bp.stats.waves_fwd}", flush=True)
+    bs = B.Solver(bp)
+    bs.iterate(T)
+    hist = bs.lb_history(T + 1)
+    lam = bs.get_lambda().cpu().numpy()
+    inst = bs.instance_bounds()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(hist))
+    assert np.all(np.diff(hist) >= -1e-6 * np.maximum(np.abs(hist[1:]), 1.0))
+    assert inst.sum() == pytest.approx(hist[-1], rel=1e-12, abs=1e-6)
+    var_off, row_off, inc_off = bp.instances()
+    del bs
+    torch.cuda.empty_cache()
+    sizes = [q.n for q in insts]
+    tomo = [k for k, q in enumerate(insts) if q.name.startswith("tomo")]
+    small = min(tomo, key=lambda k: sizes[k])
+    for k in sorted({0, 1, small, len(insts) - 2, len(insts) - 1}):
+        print(f"[batch full] instance {k} {insts[k].name}", flush=True)
+        s = B.Solver(B.Plan(B.Problem.from_ilp(insts[k])))
+        s.iterate(T)
+        assert np.array_equal(lam[inc_off[k]:inc_off[k + 1]], s.get_lambda().cpu().numpy()), k
+        del s
+    q = insts[small]
+    o = Oracle(q)
+    o.init()
+    tr = o.iterate(T)
+    assert inst[small] == pytest.approx(tr[-1], rel=1e-4, abs=1e-4)
+    lam_ref = o.lam()
+    assert_incidence_close(lam[inc_off[small]:inc_off[small + 1]], lam_ref, incidence_scale(q, lam_ref),
+                           what="lambda (smallest tomography instance)")

@@ -68,7 +68,7 @@ typedef struct {
   int32_t order_mode;     /* 0: the problem's order (identity if none set); 1: greedy colouring */
   int32_t hist_cap;       /* bound history ring length on the device (default 4096)           */
   int64_t node_budget;    /* max total BDD nodes, 0 = unlimited                                */
-  double stop_rel_impr;   /* reserved (iteration counts are explicit), 0                        */
+  double stop_rel_impr;   /* reserved: the stop rule is bddmp_solver_iterate_until's argument    */
   float alpha;            /* reserved for the smoothed variant, 0 = min-plus                    */
   int32_t tile_work;      /* a tile closes once its general levels hold this many own plus next-
                              level nodes (0: 2048; the node-parallel path stages up to 2048 of each) */
@@ -231,6 +231,18 @@ int32_t bddmp_solver_reset(bddmp_solver *s);
  * device bound history. Asynchronous.
  */
 int32_t bddmp_solver_iterate(bddmp_solver *s, int32_t n_iters);
+
+/*
+ * Iterates until the bound's relative improvement drops below min_rel_impr (Sec. 7: the paper
+ * stops at a minimal relative objective improvement of 1e-6): iteration t meets the rule when
+ * LB_t - LB_{t-1} < min_rel_impr * max(|LB_t|, 1). The iterations run asynchronously in blocks of
+ * check_every; after each block the stream is synchronised and the block's bounds are checked.
+ * *iters_done: iterations run (the solver's state is after them; at most max_iters, a multiple of
+ * check_every unless max_iters ends the run); *stop_at: the first iteration of this call meeting the
+ * rule (1-based), or -1; *lb: the last bound. check_every: 1 .. hist_cap - 1; min_rel_impr >= 0.
+ */
+int32_t bddmp_solver_iterate_until(bddmp_solver *s, int32_t max_iters, double min_rel_impr, int32_t check_every,
+                                   int32_t *iters_done, int32_t *stop_at, double *lb);
 
 /*
  * Latest bound, dual-feasibility residual max_i |c_i - sum_j lambda^j_i| and the bound valid

@@ -83,6 +83,7 @@ SIGNATURES = {
     "bddmp_solver_min_marginals": (_I32, [_P, _P, _P]),
     "bddmp_solver_get_lambda": (_I32, [_P, _P]),
     "bddmp_solver_set_lambda": (_I32, [_P, _P]),
+    "bddmp_solver_iterate_until": (_I32, [_P, _I32, _D, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_D)]),
     "bddmp_solver_get_copy_duals": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_solver_set_copy_duals": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_solver_round_primal": (_I32, [_P, _P, _P, C.POINTER(_D), C.POINTER(_I64)]),
@@ -297,6 +298,13 @@ def bddmp_solver_set_lambda(h, lam):
     _check(lib().bddmp_solver_set_lambda(h, _dptr(lam)))
 
 
+def bddmp_solver_iterate_until(h, max_iters: int, min_rel_impr: float, check_every: int):
+    done, at, lb = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().bddmp_solver_iterate_until(h, int(max_iters), float(min_rel_impr), int(check_every), C.byref(done),
+                                            C.byref(at), C.byref(lb)))
+    return done.value, at.value, lb.value
+
+
 def bddmp_solver_get_copy_duals(h, mu_bar, mu, dfw, dbw):
     _check(lib().bddmp_solver_get_copy_duals(h, _dptr(mu_bar), _dptr(mu), _dptr(dfw), _dptr(dbw)))
 
@@ -469,6 +477,10 @@ class Solver:
 
     def iterate(self, n_iters: int):
         bddmp_solver_iterate(self.h, n_iters)
+
+    def iterate_until(self, max_iters: int, min_rel_impr: float = 1e-6, check_every: int = 10):
+        """(iterations run, first iteration meeting the stop rule or -1, last bound)."""
+        return bddmp_solver_iterate_until(self.h, max_iters, min_rel_impr, check_every)
 
     def lower_bound(self):
         return bddmp_solver_lower_bound(self.h)

@@ -293,6 +293,14 @@ int32_t bddmp_solver_iterate(bddmp_solver *h, int32_t n_iters) {
   return guarded([&] { return bddmp::solver_iterate(*h->s, n_iters); });
 }
 
+int32_t bddmp_solver_iterate_until(bddmp_solver *h, int32_t max_iters, double min_rel_impr, int32_t check_every,
+                                   int32_t *iters_done, int32_t *stop_at, double *lb) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] {
+    return bddmp::solver_iterate_until(*h->s, max_iters, min_rel_impr, check_every, iters_done, stop_at, lb);
+  });
+}
+
 int32_t bddmp_solver_lower_bound(bddmp_solver *h, double *lb, double *residual, double *any_lambda_bound) {
   SOLVER_OR_FAIL(h);
   return guarded([&] { return bddmp::solver_lower_bound(*h->s, lb, residual, any_lambda_bound); });

@@ -768,7 +768,8 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         live += nlive;
       }
   }
-  if (P.n_arcs_cut >= INT32_MAX || P.rarc.size() >= size_t(INT32_MAX)) return set_error(BDDMP_BDD_TOO_LARGE, "too many copy arcs");
+  if (P.n_cuts >= INT32_MAX || P.n_arcs_cut >= INT32_MAX || P.rarc.size() >= size_t(INT32_MAX))
+    return set_error(BDDMP_BDD_TOO_LARGE, "too many cuts or copy arcs");
   P.n_cut_parts = (P.n_cut_narrow + kTile - 1) / kTile + (P.n_cuts - P.n_cut_narrow + kCutsPerBlock - 1) / kCutsPerBlock;
 
   // forward tiles: positions are storage layers

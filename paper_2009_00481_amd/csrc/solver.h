@@ -14,6 +14,8 @@ struct Solver;
 int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solver *&out);
 int32_t solver_reset(Solver &S);
 int32_t solver_iterate(Solver &S, int32_t n);
+int32_t solver_iterate_until(Solver &S, int32_t max_iters, double rel, int32_t every, int32_t *done, int32_t *at,
+                             double *lb);
 int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_lambda_bound);
 int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n);
 int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out);

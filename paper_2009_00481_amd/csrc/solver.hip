@@ -320,6 +320,33 @@ int32_t solver_iterate(Solver &S, int32_t n) {
   return BDDMP_OK;
 }
 
+int32_t solver_iterate_until(Solver &S, int32_t max_iters, double rel, int32_t every, int32_t *done, int32_t *at,
+                             double *lb) {
+  const Plan &P = *S.plan;
+  if (max_iters < 0 || !(rel >= 0.0) || every < 1 || every >= P.hist_cap || !done || !at || !lb)
+    return set_error(BDDMP_INVALID_ARG, "max_iters >= 0, min_rel_impr >= 0, 1 <= check_every < hist_cap, non-null outputs");
+  std::vector<double> b(size_t(every) + 1);
+  int32_t got = 0;
+  if (int32_t rc = solver_lb_history(S, b.data(), 1, &got)) return rc;
+  double prev = got ? b[0] : 0.0;
+  int32_t n = 0;
+  *at = -1;
+  while (n < max_iters && *at < 0) {
+    const int32_t k = std::min(every, max_iters - n);
+    if (int32_t rc = solver_iterate(S, k)) return rc;
+    if (int32_t rc = solver_lb_history(S, b.data(), k, &got)) return rc;
+    for (int32_t q = 0; q < got && *at < 0; ++q) {
+      if (b[size_t(q)] - prev < rel * std::max(std::fabs(b[size_t(q)]), 1.0)) *at = n + q + 1;
+      prev = b[size_t(q)];
+    }
+    prev = b[size_t(got - 1)];
+    n += k;
+  }
+  *done = n;
+  *lb = prev;
+  return BDDMP_OK;
+}
+
 int32_t solver_set_graphs(Solver &S, int32_t enable) {
   S.use_graph = enable != 0;
   if (!S.use_graph) drop_graph(S);

@@ -191,3 +191,24 @@ def test_full_size_mrf_workload():
     assert hist[-1] > hist[0]
     assert resid <= 1e-4 * float(np.abs(ilp.cost).max())
     assert any_lb <= lb + 1e-9
+
+
+def test_iterate_until_stop_rule():
+    """Sec. 7's stop rule: the first iteration whose bound improves by less than 1e-6 relative,
+    found from the bound history of a plain run of the same length."""
+    ilp = I.config(1)
+    a = B.Solver(B.Plan(B.Problem.from_ilp(ilp)))
+    done, at, lb = a.iterate_until(400, 1e-6, 10)
+    h = a.lb_history(done + 1)
+    impr = np.diff(h) < 1e-6 * np.maximum(np.abs(h[1:]), 1.0)
+    want = int(np.argmax(impr)) + 1 if impr.any() else -1
+    assert at == want
+    assert done == (400 if at < 0 else min(400, ((at + 9) // 10) * 10))
+    assert lb == h[-1]
+    b = B.Solver(B.Plan(B.Problem.from_ilp(ilp)))
+    b.iterate(done)
+    assert np.array_equal(a.get_lambda().cpu().numpy(), b.get_lambda().cpu().numpy())
+    with pytest.raises(B.BddmpError):
+        a.iterate_until(10, 1e-6, 0)
+    with pytest.raises(B.BddmpError):
+        a.iterate_until(10, -1.0, 5)

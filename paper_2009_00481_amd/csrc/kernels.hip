@@ -229,6 +229,20 @@ __device__ __forceinline__ float group_bstep(const Dev &D, const GenTile &T, int
   return r;
 }
 
+// The layer holding node t of a tile's concatenated levels: the largest k < n with off[k] <= t
+// (off: exclusive prefix sums of the levels' widths, so non-decreasing with off[0] = 0; a level of
+// width 0 repeats its successor's offset and is passed over). A fixed-step binary search: every
+// lane takes the same 8 LDS reads, and searches for different nodes of a lane overlap.
+__device__ __forceinline__ int layer_of_node(const int *off, int n, int t) {
+  int k = 0;
+#pragma unroll
+  for (int step = kTile / 2; step > 0; step >>= 1) {
+    const int c = k + step;
+    if (c < n && off[c] <= t) k = c;
+  }
+  return k;
+}
+
 // Flat path: the tile's general nodes spread over all lanes (node t of the concatenated own
 // levels, kFlatR per lane), with the child levels' backward messages and the own levels' forward
 // messages staged in LDS. A layer's min-marginals are integer minima in LDS (exact).
@@ -253,7 +267,6 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   __shared__ std::conditional_t<NARROW_ONLY, int, GenTile> s_g;
   __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap], s_fu[NARROW_ONLY ? 1 : kFlatCap];
   // flat path: the layer holding the first node of each 64-node chunk (own and next-level nodes)
-  __shared__ uint8_t s_cko[NARROW_ONLY ? 1 : kFlatCap / 64], s_ckc[NARROW_ONLY ? 1 : kFlatCap / 64];
   const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
   const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
   const uint32_t w0 = uint32_t(tiles[2 * tix]);
@@ -341,13 +354,6 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     mode = int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
     flat = mode == int(kFlat) && TW <= kFlatCap && TC <= kFlatCap;
     G = mode == int(kFlat) ? 64 : (1 << mode);
-    if (flat && gen) {
-      // chunk table: this layer holds the first node of chunks ceil(wo/64) .. floor((wo+w-1)/64)
-      const int o0 = T.wo[myk], c0 = T.co[myk];
-      for (int c = (o0 + 63) >> 6; c <= (o0 + w - 1) >> 6; ++c) s_cko[c] = uint8_t(myk);
-      if (wc > 0)
-        for (int c = (c0 + 63) >> 6; c <= (c0 + wc - 1) >> 6; ++c) s_ckc[c] = uint8_t(myk);
-    }
     __syncthreads();
     if (flat) {
       // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
@@ -357,8 +363,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         kr[r] = -1;
         const int t = s + r * kTile;
         if (r * kTile < TW && t < TW) {
-          int k = s_cko[t >> 6];
-          while (k + 1 < ngen && T.wo[k + 1] <= t) ++k;
+          const int k = layer_of_node(T.wo, ngen, t);
           const int u = t - T.wo[k];
           kr[r] = k;
           ar[r] = D.garcs[T.os[k] + u];
@@ -371,8 +376,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         kc[r] = -1;
         pkc[r] = kManyInArcs;
         if (r * kTile < TC && t < TC) {
-          int k = s_ckc[t >> 6];
-          while (k + 1 < ngen && T.co[k + 1] <= t) ++k;
+          const int k = layer_of_node(T.co, ngen, t);
           kc[r] = k;
           s_cb[t] = D.mbc[T.cs[k] + (t - T.co[k])];
           if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];

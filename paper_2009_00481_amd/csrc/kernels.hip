@@ -370,18 +370,25 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
           fr[r] = D.mf[T.os[k] + u];
         }
       }
+      // all loads of the lane first, then the LDS stores: a store right after its load would wait
+      // for that load before the next one issues
+      float cbr[kFlatR];
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         const int t = s + r * kTile;
         kc[r] = -1;
         pkc[r] = kManyInArcs;
+        cbr[r] = 0.0f;
         if (r * kTile < TC && t < TC) {
           const int k = layer_of_node(T.co, ngen, t);
           kc[r] = k;
-          s_cb[t] = D.mbc[T.cs[k] + (t - T.co[k])];
+          cbr[r] = D.mbc[T.cs[k] + (t - T.co[k])];
           if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];
         }
       }
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r)
+        if (kc[r] >= 0) s_cb[s + r * kTile] = cbr[r];
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {

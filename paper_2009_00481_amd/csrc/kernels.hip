@@ -402,17 +402,20 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
           o1 = ord_of((fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16));
           s_fu[s + r * kTile] = fr[r];
         }
-        // a wavefront whose 64 nodes all belong to one layer reduces first (one LDS atomic
-        // instead of 64 on one word); integer min of the order-preserving codes is exact
-        const int k0 = __shfl(k, 0, 64), k63 = __shfl(k, 63, 64);
-        if (k0 == k63 && k0 >= 0) {
-          o0 = __reduce_min_sync(~0ull, o0);
-          o1 = __reduce_min_sync(~0ull, o1);
-          if (lane == 0) {
-            atomicMin(&T.m0[k0], o0);
-            atomicMin(&T.m1[k0], o1);
+        // segmented minimum over the runs of equal k in the wavefront (a layer's nodes sit on
+        // consecutive lanes), then one LDS atomic per run head instead of one per node; integer
+        // min of the order-preserving codes is exact
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const unsigned w0 = __shfl_down(o0, off, 64), w1 = __shfl_down(o1, off, 64);
+          const int kk = __shfl_down(k, off, 64);
+          if (lane + off < 64 && kk == k) {
+            o0 = min(o0, w0);
+            o1 = min(o1, w1);
           }
-        } else if (k >= 0) {
+        }
+        const int kp = __shfl_up(k, 1, 64);
+        if (k >= 0 && (lane == 0 || kp != k)) {
           atomicMin(&T.m0[k], o0);
           atomicMin(&T.m1[k], o1);
         }

@@ -137,11 +137,20 @@ struct Layer {
 // General layers of a tile. Their records are read once by the layer's own lane and kept in LDS
 // by compact index k (the layer's rank among the tile's general layers, in position order).
 struct GenTile {
-  int os[kTile], cs[kTile], ww[kTile], rb[kTile], osc[kTile], pcs[kTile];
+  int os[kTile], cs[kTile], ww[kTile];
+  // forward tiles use the child layer's own slot and the in-arc base, backward tiles the parent's
+  // child slot and node 0's new backward message (the root value on a root level)
+  union {
+    int osc[kTile];
+    int pcs[kTile];
+  };
+  union {
+    int rb[kTile];
+    float e[kTile];
+  };
   int wo[kTile + 1], co[kTile + 1];  // exclusive prefix sums of own / child level widths
   float lam[kTile];
   unsigned m0[kTile], m1[kTile];     // min-marginals as order-preserving integers
-  float e[kTile];                    // new backward message of node 0 (the root value on a root level)
 };
 
 // float <-> unsigned with the same order (for integer min in LDS; a bijection, so exact)
@@ -260,12 +269,27 @@ __device__ __forceinline__ float staged(const float *cb, int c0, uint32_t c) {
 template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
 __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0) {
   __shared__ float s_d[kTile];
-  __shared__ float s_share[kTile];
-  __shared__ int s_nf[kTile];
   __shared__ int s_wcnt[kTile / 64];
   // LDS of the general-layer paths (one element in narrow-only instantiations)
   __shared__ std::conditional_t<NARROW_ONLY, int, GenTile> s_g;
-  __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap], s_fu[NARROW_ONLY ? 1 : kFlatCap];
+  // J_i shares and forced-row counts; with general layers they reuse the min-marginal words, which
+  // are read before the update begins (fewer LDS bytes per workgroup, more workgroups per CU)
+  __shared__ float s_share_n[NARROW_ONLY ? kTile : 1];
+  __shared__ int s_nf_n[NARROW_ONLY ? kTile : 1];
+  float *s_share;
+  int *s_nf;
+  if constexpr (NARROW_ONLY) {
+    s_share = s_share_n;
+    s_nf = s_nf_n;
+  } else {
+    s_share = reinterpret_cast<float *>(s_g.m0);
+    s_nf = reinterpret_cast<int *>(s_g.m1);
+  }
+  // flat path: the next levels' backward messages; in a forward tile, once the min-marginals are
+  // taken, the own levels' forward messages for the pull (one array serves both, so that more
+  // workgroups fit a CU's LDS)
+  __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap];
+  float *const s_fu = s_cb;
   // flat path: the layer holding the first node of each 64-node chunk (own and next-level nodes)
   const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
   const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
@@ -343,9 +367,12 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
       T.os[myk] = grec.x;
       T.cs[myk] = grec.y;
       T.ww[myk] = grec.z;
-      T.rb[myk] = grec.w;
-      T.osc[myk] = gnb.x;
-      T.pcs[myk] = gnb.y;
+      if (DIR == kFwd) {
+        T.rb[myk] = grec.w;
+        T.osc[myk] = gnb.x;
+      } else {
+        T.pcs[myk] = gnb.y;
+      }
       T.wo[myk] = woff + iw - w;
       T.co[myk] = coff + ic - wc;
       T.lam[myk] = ly.lam0;
@@ -400,7 +427,6 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
           const float lam0 = T.lam[k];
           o0 = ord_of(fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu));
           o1 = ord_of((fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16));
-          s_fu[s + r * kTile] = fr[r];
         }
         // segmented minimum over the runs of equal k in the wavefront (a layer's nodes sit on
         // consecutive lanes), then one LDS atomic per run head instead of one per node; integer
@@ -434,6 +460,12 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     if (gen) {
       ly.m0 = float_of(T.m0[myk]);
       ly.m1 = float_of(T.m1[myk]);
+    }
+    if (DIR == kFwd && flat) {
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r)
+        if (kr[r] >= 0) s_fu[s + r * kTile] = fr[r];
+      // the pull below reads them after the barrier that publishes the new multipliers
     }
   }
 

@@ -256,7 +256,9 @@ int32_t bddmp_solver_lower_bound(bddmp_solver *s, double *lb, double *residual, 
  * of E^j (problem (D)) plus the sum of min(0, c_i) over its variables in no row. E^j is recomputed
  * from the root level's messages with the sweep's own operations, and each instance's rows are
  * summed in one fixed shape, so a batched plan gives bitwise the values of each instance's own
- * plan. lb_host: host [n], n must equal n_instances. Synchronises.
+ * plan. With a split (Sec. 6) the sub-BDDs after the instance's cuts add their E as the last
+ * backward copy-arc update left it, in canonical cut order. lb_host: host [n], n must equal
+ * n_instances. Synchronises.
  */
 int32_t bddmp_solver_instance_bounds(bddmp_solver *s, double *lb_host, int32_t n);
 

@@ -88,7 +88,7 @@ struct ArenaLayout {
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
   size_t inst_row, inst_lb;
-  size_t cuts, cut_slots, cut_live, cut_rb, cut_arc, mu_in, dfw, dbw;
+  size_t cuts, cut_slots, cut_live, cut_rb, cut_arc, mu_in, dfw, dbw, cut_e, inst_cut, inst_cut_idx;
   size_t total;
 };
 
@@ -165,6 +165,10 @@ struct Plan {
   int64_t n_cuts = 0, n_cut_narrow = 0, n_arcs_cut = 0, n_copy = 0, n_cut_parts = 0;
   std::vector<int32_t> var_interval;  // [n] interval of each variable (split only)
   std::vector<int32_t> cuts, cut_slots, cut_live, cut_rb;
+  // per instance: its cut records in canonical order (offsets [n_inst + 1], record indices), for
+  // the per-instance bounds (the sub-BDD after a cut adds its E to its row's instance)
+  std::vector<int32_t> inst_cut, inst_cut_idx;
+  std::vector<int32_t> cut_row;       // [n_cuts] row of each cut record (host)
   std::vector<uint16_t> cut_arc;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes

@@ -54,6 +54,8 @@ struct Dev {
   const int32_t *cut_live, *cut_rb;
   const uint16_t *cut_arc;
   float *mu_in, *dfw, *dbw;
+  float *cut_e;               // E of the sub-BDD after each cut (written by the backward copy update)
+  const int32_t *inst_cut, *inst_cut_idx;  // each instance's cut records (offsets, record indices)
   float gamma;
 };
 

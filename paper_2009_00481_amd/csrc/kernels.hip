@@ -698,6 +698,8 @@ __global__ __launch_bounds__(256) void instance_bound_kernel(const Dev D) {
     }
     acc += double(e);
   }
+  // the sub-BDDs after the instance's cuts (Sec. 6), as the last backward copy update left them
+  for (int q = D.inst_cut[k] + int(threadIdx.x); q < D.inst_cut[k + 1]; q += 256) acc += double(D.cut_e[D.inst_cut_idx[q]]);
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) D.inst_lb[k] = t;
 }

@@ -330,6 +330,22 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     if (!f) return "cut arcs not covered";
   for (uint8_t f : live_seen)
     if (!f) return "copy pairs not covered";
+  // instance cut lists: every record once, inside its row's instance, canonical order
+  if (P.inst_cut.size() != P.inst_row32.size() || int64_t(P.inst_cut_idx.size()) != nc) return "instance cuts";
+  {
+    std::vector<uint8_t> seen(static_cast<size_t>(nc), 0);
+    for (size_t k = 0; k + 1 < P.inst_cut.size(); ++k) {
+      if (P.inst_cut[k + 1] < P.inst_cut[k]) return "instance cuts";
+      for (int32_t q = P.inst_cut[k]; q < P.inst_cut[k + 1]; ++q) {
+        const int32_t c = P.inst_cut_idx[size_t(q)];
+        if (c < 0 || c >= nc || seen[size_t(c)]++) return "instance cut index";
+        const int32_t row = P.cut_row[size_t(c)];
+        if (row < P.inst_row32[k] || row >= P.inst_row32[k + 1]) return "instance cut row";
+        if (q > P.inst_cut[k] && P.canon_of[P.cuts[4 * size_t(c)]] <= P.canon_of[P.cuts[4 * size_t(P.inst_cut_idx[size_t(q - 1)])]])
+          return "instance cut order";
+      }
+    }
+  }
   // instance row ranges: from 0 to m, non-decreasing (the bound kernel reads rows inside them)
   const size_t ni = P.inst_row32.size();
   if (ni < 2 || P.inst_row32[0] != 0 || P.inst_row32[ni - 1] != P.m || P.inst_lb_const.size() != ni - 1)
@@ -755,6 +771,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
                                                  int32_t(P.own_slot[Lr]), int32_t(P.cslot[Lr])});
           P.cut_live.push_back(int32_t(live));
           P.cut_rb.push_back(rb);
+          P.cut_row.push_back(j);
           P.n_cut_narrow += narrow;
         }
         if (pass == 0) {
@@ -867,6 +884,23 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     for (int64_t i = P.inst_var[k]; i < P.inst_var[k + 1]; ++i)
       if (!P.var_nj[size_t(i)] && p.cost[size_t(i)] < 0) P.inst_lb_const[k] += p.cost[size_t(i)];
 
+  // each instance's cut records in canonical (row, level) order
+  {
+    std::vector<int32_t> order_c(static_cast<size_t>(P.n_cuts));
+    std::iota(order_c.begin(), order_c.end(), 0);
+    std::stable_sort(order_c.begin(), order_c.end(), [&](int32_t a, int32_t b) {
+      return P.canon_of[P.cuts[4 * size_t(a)]] < P.canon_of[P.cuts[4 * size_t(b)]];
+    });
+    P.inst_cut.assign(n_inst + 1, 0);
+    P.inst_cut_idx.clear();
+    size_t q = 0;
+    for (size_t k = 0; k < n_inst; ++k) {
+      P.inst_cut[k] = int32_t(P.inst_cut_idx.size());
+      while (q < order_c.size() && P.cut_row[size_t(order_c[q])] < P.inst_row[k + 1]) P.inst_cut_idx.push_back(order_c[q++]);
+    }
+    P.inst_cut[n_inst] = int32_t(P.inst_cut_idx.size());
+  }
+
   // arena layout
   ArenaLayout &A = P.lay;
   size_t off = 0;
@@ -919,6 +953,9 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.mu_in = take(4 * na);
   A.dfw = take(4 * na);
   A.dbw = take(4 * na);
+  A.cut_e = take(4 * size_t(P.n_cuts));
+  A.inst_cut = take(4 * P.inst_cut.size());
+  A.inst_cut_idx = take(4 * P.inst_cut_idx.size());
   A.total = off;
   const std::string bad = validate_layout(P, ownw, childw, level, exit_cut, root_cut);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);

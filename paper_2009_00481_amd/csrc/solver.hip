@@ -236,6 +236,9 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.mu_in = reinterpret_cast<float *>(b + A.mu_in);
   D.dfw = reinterpret_cast<float *>(b + A.dfw);
   D.dbw = reinterpret_cast<float *>(b + A.dbw);
+  D.cut_e = reinterpret_cast<float *>(b + A.cut_e);
+  D.inst_cut = reinterpret_cast<const int32_t *>(b + A.inst_cut);
+  D.inst_cut_idx = reinterpret_cast<const int32_t *>(b + A.inst_cut_idx);
   D.gamma = P.split_gamma;
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
@@ -270,6 +273,8 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.cut_slots, P.cut_slots.data(), 4 * P.cut_slots.size()),
       up(A.cut_live, P.cut_live.data(), 4 * P.cut_live.size()),
       up(A.cut_rb, P.cut_rb.data(), 4 * P.cut_rb.size()),
+      up(A.inst_cut, P.inst_cut.data(), 4 * P.inst_cut.size()),
+      up(A.inst_cut_idx, P.inst_cut_idx.data(), 4 * P.inst_cut_idx.size()),
       up(A.cut_arc, P.cut_arc.data(), 2 * P.cut_arc.size()),
   };
   for (hipError_t e : errs)
@@ -374,7 +379,6 @@ int32_t solver_instance_bounds(Solver &S, double *lb_host, int32_t n) {
   const Plan &P = *S.plan;
   const int32_t n_inst = int32_t(P.inst_lb_const.size());
   if (S.costs_replaced) return set_error(BDDMP_BAD_STATE, "instance bounds use the plan's costs; costs were replaced");
-  if (P.n_cuts) return set_error(BDDMP_BAD_STATE, "instance bounds are not kept for a split plan");
   if (!lb_host || n != n_inst)
     return set_error(BDDMP_INVALID_ARG, "lb array must hold n_instances = " + std::to_string(n_inst) + " values");
   if (int32_t rc = launched(launch_instance_bounds(S.D, n_inst, S.stream), "instance_bounds")) return rc;

@@ -145,7 +145,9 @@ __global__ __launch_bounds__(256) void copy_bwd_narrow_kernel(const Dev D, int n
     }
     D.mf[sl.z] = f0;
     if (wr > 1) D.mf[sl.z + 1] = f1;
-    e = double(fminf(f0 + n0, f1 + n1));
+    const float en = fminf(f0 + n0, f1 + n1);
+    D.cut_e[c] = en;
+    e = double(en);
   }
   const double t = block_sum(e, sh);
   if (threadIdx.x == 0) D.lbpart[part0 + int(blockIdx.x)] = t;
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(256) void copy_bwd_wide_kernel(const Dev D, int nn,
     }
   }
   for (int o = 32; o > 0; o >>= 1) en = fminf(en, __shfl_xor(en, o, 64));
+  if (on && lane == 0) D.cut_e[c] = en;
   const double t = block_sum((on && lane == 0) ? double(en) : 0.0, sh);
   if (threadIdx.x == 0) D.lbpart[part0 + int(blockIdx.x)] = t;
 }

@@ -88,7 +88,7 @@ struct ArenaLayout {
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
   size_t inst_row, inst_lb;
-  size_t cuts, cut_slots, cut_live, cut_rb, cut_arc, mu_in, dfw, dbw, cut_e, inst_cut, inst_cut_idx;
+  size_t cuts, cut_slots, cut_live, cut_rb, cut_arc, mu_in, dfw, dbw, cut_e, inst_cut, inst_cut_idx, exit_rec;
   size_t total;
 };
 
@@ -169,6 +169,7 @@ struct Plan {
   // the per-instance bounds (the sub-BDD after a cut adds its E to its row's instance)
   std::vector<int32_t> inst_cut, inst_cut_idx;
   std::vector<int32_t> cut_row;       // [n_cuts] row of each cut record (host)
+  std::vector<int32_t> exit_rec;      // [I] with a split: the cut record whose exit layer this is, or -1
   std::vector<uint16_t> cut_arc;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes

@@ -56,6 +56,7 @@ struct Dev {
   float *mu_in, *dfw, *dbw;
   float *cut_e;               // E of the sub-BDD after each cut (written by the backward copy update)
   const int32_t *inst_cut, *inst_cut_idx;  // each instance's cut records (offsets, record indices)
+  const int32_t *exit_rec;    // per layer: the cut record it is the exit layer of, or -1 (null: no split)
   float gamma;
 };
 

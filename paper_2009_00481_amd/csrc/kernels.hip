@@ -788,7 +788,12 @@ __global__ __launch_bounds__(256) void violation_kernel(const Dev D, int m) {
     for (int c = c0; c < c1; ++c) {
       const int L = D.layer_of[c];
       const uint32_t a = D.garcs[slot];
-      const uint32_t ch = D.xbuf[D.layer_var[L]] ? (a >> 16) : (a & 0xFFFFu);
+      uint32_t ch = D.xbuf[D.layer_var[L]] ? (a >> 16) : (a & 0xFFFFu);
+      // an exit layer of a split codes its live arcs by their copy-arc slot: back to the child
+      if (D.exit_rec && ch < kTop) {
+        const int r = D.exit_rec[L];
+        if (r >= 0) ch = D.cut_arc[D.cuts[r].z + int(ch)];
+      }
       if (ch == kBot) {
         bad += 1.0;
         break;

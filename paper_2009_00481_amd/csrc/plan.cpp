@@ -330,6 +330,17 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     if (!f) return "cut arcs not covered";
   for (uint8_t f : live_seen)
     if (!f) return "copy pairs not covered";
+  // exit layers name their cut records
+  if (nc) {
+    if (int64_t(P.exit_rec.size()) != I) return "exit records";
+    int64_t nexit = 0;
+    for (int64_t L = 0; L < I; ++L) {
+      const int32_t r = P.exit_rec[size_t(L)];
+      if (r < -1 || r >= nc || (r >= 0) != bool(exit_cut[L]) || (r >= 0 && P.cuts[4 * size_t(r)] != L)) return "exit records";
+      nexit += r >= 0;
+    }
+    if (nexit != nc) return "exit records";
+  }
   // instance cut lists: every record once, inside its row's instance, canonical order
   if (P.inst_cut.size() != P.inst_row32.size() || int64_t(P.inst_cut_idx.size()) != nc) return "instance cuts";
   {
@@ -884,6 +895,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     for (int64_t i = P.inst_var[k]; i < P.inst_var[k + 1]; ++i)
       if (!P.var_nj[size_t(i)] && p.cost[size_t(i)] < 0) P.inst_lb_const[k] += p.cost[size_t(i)];
 
+  // the cut record of each exit layer (the row-violation walk maps its virtual arc codes back)
+  if (P.n_cuts) {
+    P.exit_rec.assign(static_cast<size_t>(I), -1);
+    for (int64_t c = 0; c < P.n_cuts; ++c) P.exit_rec[size_t(P.cuts[4 * size_t(c)])] = int32_t(c);
+  }
   // each instance's cut records in canonical (row, level) order
   {
     std::vector<int32_t> order_c(static_cast<size_t>(P.n_cuts));
@@ -956,6 +972,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.cut_e = take(4 * size_t(P.n_cuts));
   A.inst_cut = take(4 * P.inst_cut.size());
   A.inst_cut_idx = take(4 * P.inst_cut_idx.size());
+  A.exit_rec = take(4 * P.exit_rec.size());
   A.total = off;
   const std::string bad = validate_layout(P, ownw, childw, level, exit_cut, root_cut);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);

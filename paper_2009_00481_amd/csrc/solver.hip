@@ -239,6 +239,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.cut_e = reinterpret_cast<float *>(b + A.cut_e);
   D.inst_cut = reinterpret_cast<const int32_t *>(b + A.inst_cut);
   D.inst_cut_idx = reinterpret_cast<const int32_t *>(b + A.inst_cut_idx);
+  D.exit_rec = P.exit_rec.empty() ? nullptr : reinterpret_cast<const int32_t *>(b + A.exit_rec);
   D.gamma = P.split_gamma;
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
@@ -275,6 +276,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.cut_rb, P.cut_rb.data(), 4 * P.cut_rb.size()),
       up(A.inst_cut, P.inst_cut.data(), 4 * P.inst_cut.size()),
       up(A.inst_cut_idx, P.inst_cut_idx.data(), 4 * P.inst_cut_idx.size()),
+      up(A.exit_rec, P.exit_rec.data(), 4 * P.exit_rec.size()),
       up(A.cut_arc, P.cut_arc.data(), 2 * P.cut_arc.size()),
   };
   for (hipError_t e : errs)

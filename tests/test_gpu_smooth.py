@@ -209,3 +209,25 @@ def test_smooth_argument_errors():
     with pytest.raises(B.BddmpError) as e:
         s.instance_bounds()
     assert e.value.code == -7
+
+
+def test_full_size_differentiable_workload():
+    """The 128x128, 4-label Potts workload at full size, as the benchmark runs it (50 iterations, one
+    checkpoint per iteration): the first smoothed bounds against the fp64 oracle, the whole trace
+    non-decreasing, and a finite gradient (its values are checked against the oracle's adjoint and
+    finite differences on the smaller instances above)."""
+    import torch
+
+    ilp = I.config(5)
+    alpha, T = 0.1, 50
+    print(f"[smooth full] n={ilp.n} T={T}", flush=True)
+    r = _gpu_smooth(ilp, alpha, T)
+    o = Oracle(ilp)
+    lb0 = o.smooth_init(alpha)
+    tr = np.concatenate([[lb0], o.smooth_iterate(alpha, 2)])
+    assert_trace_close(r["hist"][:3], tr)
+    h = r["hist"]
+    assert np.all(np.diff(h) >= -1e-6 * np.maximum(np.abs(h[1:]), 1.0))
+    g = r["grad"]
+    assert np.all(np.isfinite(g))
+    torch.cuda.synchronize()

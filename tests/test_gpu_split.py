@@ -94,6 +94,7 @@ def test_split_bitwise_against_fp32_mirror(name, K, order_mode):
     assert np.array_equal(g["m1"], r["m1"])
     assert np.array_equal(g["M"], r["M"])
     assert np.array_equal(g["x"], r["x"])
+    assert g["nviol"] == r["nviol"]
     cd = r["o"].copy_duals()
     mub, mu, dfw, dbw = (t.cpu().numpy().astype(np.float64) for t in g["solver"].copy_duals())
     assert np.array_equal(mub, cd["mu_bar"])

@@ -97,3 +97,40 @@ def test_random_batches_equal_their_instances():
             assert np.array_equal(lam[inc[k]:inc[k + 1]], s.get_lambda().cpu().numpy()), (trial, k)
             assert inst[k] == s.instance_bounds()[0], (trial, k)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("block", range(2))
+def test_random_wide_rows_any_general_path(block):
+    """Long rows with large coefficients (levels of tens to hundreds of nodes, the general-layer
+    paths), a random choice of lanes per width class: bitwise equal to the float mirror."""
+    import torch
+
+    checked = 0
+    for seed in range(block * 12, block * 12 + 12):
+        rng = np.random.default_rng(5000 + seed)
+        n = int(rng.integers(20, 120))
+        ilp = I.random_ilp(n, int(rng.integers(4, 30)), kmin=2, kmax=int(rng.integers(8, 40)),
+                           cmax=int(rng.integers(2, 7)), seed=7000 + seed)
+        om, K, T = int(rng.integers(0, 2)), int(rng.choice([0, 0, 3])), int(rng.integers(2, 8))
+        try:
+            plan = B.Plan(B.Problem.from_ilp(ilp), order_mode=om, n_intervals=K, node_budget=2_000_000)
+        except B.BddmpError:
+            continue
+        s = B.Solver(plan)
+        lanes = [int(rng.choice([0, 1, 2, 4, 8, 16, 32, 64])) for _ in range(4)]
+        s.set_groups(lanes)
+        s.iterate(T)
+        lam = s.get_lambda().cpu().numpy().astype(np.float64)
+        m0, m1 = (t.cpu().numpy().astype(np.float64) for t in s.min_marginals())
+        torch.cuda.synchronize()
+        q = I.ILP(ilp.n, ilp.cost, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, plan.order())
+        o = Oracle(q, precision="f32", split=K)
+        o.init()
+        o.iterate(T)
+        r0, r1 = o.min_marginals()
+        ctx = (seed, om, K, T, lanes, plan.stats.max_width)
+        assert np.array_equal(lam, o.lam()), ctx
+        assert np.array_equal(m0, r0) and np.array_equal(m1, r1), ctx
+        checked += 1
+    print(f"[fuzz wide] block {block}: {checked} instances", flush=True)
+    assert checked >= 8

@@ -231,3 +231,31 @@ def test_full_size_differentiable_workload():
     g = r["grad"]
     assert np.all(np.isfinite(g))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.1])
+def test_random_instances_smoothed_and_gradient(alpha):
+    """Random small ILPs (rows of 1-9 variables, coefficients up to +-3, all senses): the smoothed
+    bound trace and multipliers against the fp64 oracle, and the gradient against the oracle's fp64
+    adjoint, at the bars above."""
+    checked = 0
+    for seed in range(20):
+        rng = np.random.default_rng(300 + seed)
+        ilp = I.random_ilp(int(rng.integers(8, 50)), int(rng.integers(4, 35)), kmin=1, kmax=int(rng.integers(2, 10)),
+                           cmax=int(rng.integers(1, 4)), seed=900 + seed)
+        T = int(rng.integers(1, 8))
+        try:
+            r = _gpu_smooth(ilp, alpha, T)
+        except B.BddmpError as e:
+            assert e.code == -5
+            continue
+        o = Oracle(ilp)
+        lb0 = o.smooth_init(alpha)
+        assert_trace_close(r["hist"], np.concatenate([[lb0], o.smooth_iterate(alpha, T)]))
+        lam_ref = o.lam()
+        assert_incidence_close(r["lam"], lam_ref, incidence_scale(ilp, lam_ref), what=f"lambda seed {seed}")
+        g_ref, _ = Oracle(ilp).smooth_grad(alpha, T)
+        err = np.abs(r["grad"] - g_ref).max() / max(1.0, np.abs(g_ref).max())
+        assert err <= _grad_tol(T, r["plan"].stats.max_rows_per_var), (seed, err)
+        checked += 1
+    assert checked >= 15

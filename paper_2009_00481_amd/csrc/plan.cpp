@@ -560,11 +560,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.Db = std::max(P.Db, t + 1);
   }
 
-  // Storage order. Wave 1 takes its variables in processing order; every later wave sorts its
-  // variables by the storage position of their earliest parent layer (the previous level of one of
-  // their rows), ties and parentless variables by processing order. A workgroup's layers then
-  // push to and read from next-level slots that sit together, instead of cache lines shared with
-  // other workgroups (and other XCDs).
+  // Storage order. Each forward wave sorts its variables by backward wave, then by the storage
+  // position of their earliest parent layer (the previous level of one of their rows), ties and
+  // parentless variables by processing order. A workgroup's layers then push to and read from
+  // next-level slots that sit together, instead of cache lines shared with other workgroups (and
+  // other XCDs), and a backward wave reads runs of neighbouring layers.
   std::vector<std::vector<int32_t>> fw(size_t(P.Df) + 1), bw(size_t(P.Db) + 1);
   for (int32_t r = 0; r < n; ++r) {
     const int32_t i = P.order[r];
@@ -588,7 +588,9 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         const int32_t c = ilist[q];
         if (c > P.canon_off[inc_row[c]] && !cut_after[c - 1]) key = std::min<int64_t>(key, P.layer_of[c - 1]);
       }
-      keyed.emplace_back(key, P.rank[i]);
+      // first by backward wave, so that each backward wave's members sit in runs inside each forward
+      // wave (the backward pass gathers them through the index list with fewer partial cache lines)
+      keyed.emplace_back((int64_t(P.wave_b[i]) << 40) + (key == INT64_MAX ? (int64_t(1) << 40) - 1 : key), P.rank[i]);
     }
     std::sort(keyed.begin(), keyed.end());
     for (size_t q0 = 0; q0 < keyed.size(); ++q0) fw[t][q0] = P.order[keyed[q0].second];

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   uint32_t ar[NARROW_ONLY ? 1 : kFlatR];
   float fr[NARROW_ONLY ? 1 : kFlatR];
   int kr[NARROW_ONLY ? 1 : kFlatR];
+  int ur[NARROW_ONLY ? 1 : kFlatR];  // flat path: a staged own node's index in its level
   // flat path, forward: layer of each staged next-level node and its packed in-arcs, loaded with
   // the node's backward message so that the pull needs no further round trip
   int kc[NARROW_ONLY ? 1 : kFlatR];
@@ -393,6 +394,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
           const int k = layer_of_node(T.wo, ngen, t);
           const int u = t - T.wo[k];
           kr[r] = k;
+          ur[r] = u;
           ar[r] = D.garcs[T.os[k] + u];
           fr[r] = D.mf[T.os[k] + u];
         }
@@ -422,26 +424,26 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         if (r * kTile >= TW) break;
         const int k = kr[r];
         unsigned o0 = ord_of(INFINITY), o1 = o0;
+        int rest = 0;  // nodes of the same level on the following lanes
         if (k >= 0) {
           const int c0 = T.co[k];
           const float lam0 = T.lam[k];
+          rest = (T.ww[k] & 0xFFFF) - 1 - ur[r];
           o0 = ord_of(fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu));
           o1 = ord_of((fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16));
         }
-        // segmented minimum over the runs of equal k in the wavefront (a layer's nodes sit on
+        // segmented minimum over the runs of one level in the wavefront (a level's nodes sit on
         // consecutive lanes), then one LDS atomic per run head instead of one per node; integer
         // min of the order-preserving codes is exact
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
           const unsigned w0 = __shfl_down(o0, off, 64), w1 = __shfl_down(o1, off, 64);
-          const int kk = __shfl_down(k, off, 64);
-          if (lane + off < 64 && kk == k) {
+          if (lane + off < 64 && rest >= off) {
             o0 = min(o0, w0);
             o1 = min(o1, w1);
           }
         }
-        const int kp = __shfl_up(k, 1, 64);
-        if (k >= 0 && (lane == 0 || kp != k)) {
+        if (k >= 0 && (lane == 0 || ur[r] == 0)) {
           atomicMin(&T.m0[k], o0);
           atomicMin(&T.m1[k], o1);
         }

@@ -77,6 +77,7 @@ def committed_traffic(workload: str):
 
 
 _BATCH = {}
+_BATCH_CPU = {}
 
 
 def batch_instances(I, n):
@@ -140,6 +141,7 @@ def batched_vs_plain(args, B, I, torch):
     torch.cuda.empty_cache()
     arcs = 2.0 * st.n_arcs_live
     model = 40.0 * st.n_nodes + 16.0 * st.n_incidences
+    cpu = _BATCH_CPU.get("result")
     return {"workload": f"batch{n}: tomography P~U{{32..128}} (even positions) + tracking D~U{{200..2000}}",
             "instances": n, "n_nodes": int(st.n_nodes), "n_incidences": int(st.n_incidences),
             "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
@@ -150,7 +152,42 @@ def batched_vs_plain(args, B, I, torch):
             "batched_model_gbps": model / (batched_ms * 1e-3) / 1e9,
             "timed_iters": {"batched": T, "plain_per_instance": kp},
             "bitwise_equal_instances": f"{equal}/{len(sample)} sampled after {Tc} iterations",
-            "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s}}
+            "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s},
+            "cpu_oracle": cpu}
+
+
+def _oracle_instance(q, iters=3):
+    """One instance through the fp64 oracle (a worker process): build and init untimed, then iters
+    timed iterations; returns (arc-updates done, seconds)."""
+    from oracle import Oracle
+
+    o = Oracle(q)
+    o.init()
+    t = time.perf_counter()
+    o.iterate(iters)
+    return 2.0 * o.n_live_arcs * iters, time.perf_counter() - t
+
+
+def batched_cpu_oracle(insts):
+    """The oracle on a bounded sample of the batched instances, one instance per host core (at most
+    16), all running at once: arc-updates of the timed iterations over the longest worker's iteration
+    time."""
+    import multiprocessing as mp
+
+    cores = min(os.cpu_count() or 1, 16, len(insts))
+    step = max(1, len(insts) // cores)
+    sample = insts[::step][:cores]
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_instance, sample)
+    wall = time.perf_counter() - t
+    done = sum(r[0] for r in res)
+    longest = max(r[1] for r in res)
+    return {"value": done / longest, "unit": "arc-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sample)} of {len(insts)} instances (every {step}-th), 3 fp64 iterations each after "
+                      f"build and init, one process per instance, rate over the longest worker's iterations; "
+                      f"the batched GPU rate is over all {len(insts)} instances",
+            "wall_s": wall}
 
 
 def split_vs_plain(args, B, I, torch):
@@ -287,6 +324,11 @@ def main():
 
     from paper_2009_00481_amd import binding as B
     from paper_2009_00481_amd import instances as I
+
+    # the oracle baseline of the batched workload runs in worker processes: start them before this
+    # process touches the GPU
+    if not args.no_batched and not args.no_cpu_baseline and args.only in (None, "batched"):
+        _BATCH_CPU["result"] = batched_cpu_oracle(batch_instances(I, args.batch_instances)[0])
 
     if args.copy_probe_mib:
         # a plain copy kernel of known size: reads and writes copy_probe_mib MiB once each

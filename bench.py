@@ -168,6 +168,20 @@ def _oracle_instance(q, iters=3):
     return 2.0 * o.n_live_arcs * iters, time.perf_counter() - t
 
 
+def host_cpu():
+    """The host's processor model and logical core count, recorded beside each CPU figure."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1}
+
+
 def batched_cpu_oracle(insts):
     """The oracle on a bounded sample of the batched instances, one instance per host core (at most
     16), all running at once: arc-updates of the timed iterations over the longest worker's iteration
@@ -187,7 +201,7 @@ def batched_cpu_oracle(insts):
             "sample": f"{len(sample)} of {len(insts)} instances (every {step}-th), 3 fp64 iterations each after "
                       f"build and init, one process per instance, rate over the longest worker's iterations; "
                       f"the batched GPU rate is over all {len(insts)} instances",
-            "wall_s": wall}
+            "wall_s": wall, "host": host_cpu()}
 
 
 def split_vs_plain(args, B, I, torch):
@@ -444,7 +458,7 @@ def main():
         cpu = {"value": cpu_rate, "unit": "arc-updates/s", "cores": 1, "kind": "oracle",
                "sample": f"{done} fp64 iterations of the same {args.workload} instance after its init "
                          f"(oracle BDD build {build_cpu_s:.1f}s and init {init_cpu_s:.2f}s not in the rate)",
-               "s_per_iter": cpu_s / done}
+               "s_per_iter": cpu_s / done, "host": host_cpu()}
         del o
 
     # primal heuristic (Sec. 4, host) from the last step's total min-marginal differences

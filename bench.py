@@ -76,6 +76,21 @@ def committed_traffic(workload: str):
     return None
 
 
+def oracle_bounds(workload: str, T: int):
+    """The fp64 oracle's bounds LB_0..LB_T on the workload (written by
+    tests/golden/make_oracle_bounds.py), or None when they are not stored for T iterations."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "oracle_bounds.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        w = json.load(f).get("workloads", {}).get(workload)
+    if w is None or len(w["lb"]) < T + 1:
+        return None
+    return np.asarray(w["lb"][:T + 1], dtype=np.float64)
+
+
 _BATCH = {}
 _BATCH_CPU = {}
 
@@ -429,11 +444,21 @@ def main():
                 "bytes_per_launch": kb / kl, "avg_launch_us": kms / kl * 1e3,
                 "both_passes_gbs": round((kt["fwd_bytes"] + kt["bwd_bytes"]) / ((kt["fwd_ms"] + kt["bwd_ms"]) * 1e-3) / 1e9, 1)}
 
-    # time to bound: first t with LB_t >= LB* - 1e-4 max(|LB*|, 1), LB* = this run's LB_T
-    lb_star = float(hist[-1])
+    # time to bound: first t with LB_t >= LB* - 1e-4 max(|LB*|, 1). LB* is the fp64 oracle's LB_T on
+    # the same instance when it is stored for T iterations, else this run's own LB_T.
+    lb_self = float(hist[-1])
+    ref = oracle_bounds(args.workload, T)
+    lb_star = float(ref[-1]) if ref is not None else lb_self
     thr = lb_star - 1e-4 * max(abs(lb_star), 1.0)
-    t_hit = int(np.argmax(hist >= thr))
-    ttb_ms = t_hit * iter_ms
+    hit = hist >= thr
+    t_hit = int(np.argmax(hit)) if hit.any() else None
+    ttb_ms = t_hit * iter_ms if t_hit is not None else None
+    vs_oracle = None
+    if ref is not None:
+        gap = (hist - ref) / np.maximum(np.abs(ref), 1.0)
+        vs_oracle = {"oracle_lb_T": lb_star, "gpu_lb_T": lb_self, "rel_gap_T": float(gap[-1]),
+                     "max_abs_rel_gap": float(np.abs(gap).max()),
+                     "oracle_iters_to_bound": int(np.argmax(ref >= thr)) if (ref >= thr).any() else None}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -498,7 +523,9 @@ def main():
                    "n_arcs_live": int(st.n_arcs_live), "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
                    "bound_dtype": "f64"},
         "hbm_gbps_per_iter": gbps_iter, "iter_ms": iter_ms, "model_bytes_per_iter": iter_bytes,
-        "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit, "lb_final": lb_star, "lb_0": float(hist[0]),
+        "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit,
+        "lb_star_source": "oracle fp64 LB_T" if ref is not None else "this run's LB_T",
+        "bound_vs_oracle": vs_oracle, "lb_final": lb_self, "lb_0": float(hist[0]),
         "primal_obj": obj, "primal_violated_rows": int(nviol), "primal_search": search,
         "host_build_s": {"generate": gen_s, "plan": plan_s, "bind_upload": bind_s},
         "roofline": roofline, "cpu_baseline": cpu,

@@ -42,10 +42,39 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + k;
 }
 
-// Sum of one double per lane over the workgroup in a fixed shape (butterfly inside each
+// A double moved across lanes by a DPP control (both 32-bit halves; sources stay inside a row of
+// 16 lanes for the controls used here).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, false));
+  const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), lane));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum of one double per lane over a wavefront in a fixed shape, returned to every lane: lane pairs,
+// quads, half rows and rows of 16 lanes by DPP moves (every lane of a row ends with the same row
+// sum, since each step adds two equal partial sums in either order), then the four row sums in
+// order. All 64 lanes must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// Sum of one double per lane over the workgroup in a fixed shape (wave_sum inside each
 // wavefront, then the wavefront totals in order), so the result does not depend on timing.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int w = int(threadIdx.x) >> 6;
   if ((threadIdx.x & 63) == 0) sh[w] = v;
   __syncthreads();

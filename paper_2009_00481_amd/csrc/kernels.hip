@@ -555,13 +555,10 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     if (active && !gen) e = ly.bstep(D, lam1);
     if constexpr (!NARROW_ONLY)
       if (gen && (ly.meta & kMetaRootBit)) e = double(s_g.e[myk]);
-    // bound partial per wavefront: a fixed butterfly, only in tiles holding root levels (the
-    // branch is uniform over the workgroup)
+    // bound partial per wavefront: a fixed-shape wavefront sum, only in tiles holding root levels
+    // (the branch is uniform over the workgroup)
     double v = 0.0;
-    if (roots) {
-      v = e;
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    }
+    if (roots) v = wave_sum(e);
     if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
   }
 }

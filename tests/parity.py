@@ -6,7 +6,8 @@ import numpy as np
 from oracle import Oracle
 from paper_2009_00481_amd import binding as B
 
-# BASELINE tolerance of the FP32 GPU path against the FP64 oracle: relative 1e-4
+# Tolerance of the FP32 GPU path against the FP64 oracle: relative 1e-4, the precision at which the
+# benchmark's time to bound is defined
 REL = 1e-4
 
 

@@ -178,7 +178,7 @@ def test_autograd_function():
     (3.0 * lb2).backward()
     q = I.ILP(ilp.n, ilp.cost * 1.5, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs, ilp.order)
     g2_ref, lb2_ref = Oracle(q).smooth_grad(alpha, T)
-    assert float(lb2) == pytest.approx(lb2_ref, rel=REL)
+    assert float(lb2.detach()) == pytest.approx(lb2_ref, rel=REL)
     assert np.abs(cost2.grad.cpu().numpy() - 3.0 * g2_ref).max() / max(1.0, 3 * np.abs(g2_ref).max()) <= tol
 
 

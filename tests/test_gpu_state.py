@@ -11,6 +11,15 @@ from paper_2009_00481_amd import instances as I
 pytestmark = pytest.mark.gpu
 
 
+def _oracle_bounds(workload):
+    """LB_0..LB_T of the fp64 oracle on a benchmark workload (tests/golden/make_oracle_bounds.py)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_bounds.json")) as f:
+        return np.asarray(json.load(f)["workloads"][workload]["lb"], dtype=np.float64)
+
+
 def _solver(ilp, **kw):
     prob = B.Problem.from_ilp(ilp)
     plan = B.Plan(prob, **kw)
@@ -113,7 +122,8 @@ def test_time_kernels_counts_launches():
 def test_full_size_graph_matching_workload():
     """Graph matching 5000 x 5000, 10 candidates per left node, 200k linearised pairs (greedy-colour
     order, uneven right degrees, non-contiguous backward waves): 5 iterations element-wise against the
-    oracle, then 195 more checked by properties."""
+    oracle, then 195 more checked by properties and the bound trajectory against the oracle's stored
+    one."""
     import torch
 
     ilp = I.config(3)
@@ -146,6 +156,8 @@ def test_full_size_graph_matching_workload():
     torch.cuda.synchronize()
     assert hist.shape[0] == 201 and np.all(np.isfinite(hist))
     assert np.all(np.diff(hist) >= -1e-6 * np.abs(hist[1:])), np.diff(hist).min()
+    # the whole trajectory against the oracle's stored fp64 bounds of the same 200 iterations
+    assert_trace_close(hist, _oracle_bounds("gm5000x5000"), what="bound over 200 iterations")
     big = max(1.0, float(np.abs(lam_end).max()), float(np.abs(ilp.cost).max()))
     assert resid <= 6 * 200 * plan.stats.max_rows_per_var * 2.0 ** -24 * big, resid
     assert any_lb <= lb + 1e-9
@@ -154,7 +166,8 @@ def test_full_size_graph_matching_workload():
 def test_full_size_mrf_workload():
     """Potts 256x256, 8 labels (the benchmark workload) at the benchmark's launch configuration:
     the first bounds and sampled multipliers against the oracle, then the whole 500-iteration run
-    checked by properties (monotone bound within float rounding, dual feasibility, finiteness)."""
+    checked by properties (monotone bound within float rounding, dual feasibility, finiteness) and
+    its bound trajectory against the oracle's stored one."""
     import torch
 
     ilp = I.config(2)
@@ -188,6 +201,8 @@ def test_full_size_mrf_workload():
     assert hist.shape[0] == 501 and np.all(np.isfinite(hist))
     drop = np.diff(hist)
     assert np.all(drop >= -1e-6 * np.abs(hist[1:])), drop.min()
+    # the whole trajectory against the oracle's stored fp64 bounds of the same 500 iterations
+    assert_trace_close(hist, _oracle_bounds("potts256x256_L8"), what="bound over 500 iterations")
     assert hist[-1] > hist[0]
     assert resid <= 1e-4 * float(np.abs(ilp.cost).max())
     assert any_lb <= lb + 1e-9

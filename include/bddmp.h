@@ -91,6 +91,8 @@ typedef struct {
   int32_t n_intervals;          /* Sec. 6 variable intervals per instance (0: no split)    */
   int64_t n_cuts;               /* cut levels (one per sub-BDD boundary)                   */
   int64_t n_copy_pairs;         /* copy-arc pairs (live arcs leaving the cut levels)       */
+  int32_t fused_turn;           /* 1 if the last forward wave and the first backward wave run
+                                   as one launch (their levels are the rows' last levels)  */
 } bddmp_stats;
 
 typedef struct {
@@ -374,7 +376,8 @@ int32_t bddmp_solver_autotune(bddmp_solver *s, int32_t iters, int32_t *lanes);
  * forward pass, each backward pass and each bound reduction (not around single launches, so the
  * events add no gap between the waves of a pass) and reports the summed times per class, the
  * launches they cover (one per wave) and the algorithmic bytes of those passes (20 bytes per node
- * and 8 per incidence: arcs 8, messages 12, multiplier 8); then the same number of iterations as
+ * and 8 per incidence: arcs 8, messages 12, multiplier 8; with fused_turn the last forward wave's
+ * launch and bytes count with the backward pass that runs them); then the same number of iterations as
  * bddmp_solver_iterate runs them (graph replays by default) for iter_ms. The solver advances by
  * 2*n_iters iterations. Synchronises.
  */

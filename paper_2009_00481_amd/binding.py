@@ -41,7 +41,8 @@ class Stats(C.Structure):
                 ("waves_bwd", C.c_int32), ("device_bytes", C.c_int64), ("max_width", C.c_int32),
                 ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
                 ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32),
-                ("n_intervals", C.c_int32), ("n_cuts", C.c_int64), ("n_copy_pairs", C.c_int64)]
+                ("n_intervals", C.c_int32), ("n_cuts", C.c_int64), ("n_copy_pairs", C.c_int64),
+                ("fused_turn", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

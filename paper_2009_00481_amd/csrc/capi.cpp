@@ -229,6 +229,7 @@ int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   out->n_intervals = P.split_k;
   out->n_cuts = P.n_cuts;
   out->n_copy_pairs = P.n_copy;
+  out->fused_turn = P.fuse_turn ? 1 : 0;
   return BDDMP_OK;
 }
 

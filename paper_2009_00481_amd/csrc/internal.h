@@ -137,6 +137,9 @@ struct Plan {
   std::vector<int32_t> bwd_list;      // [I] backward position -> storage layer (used if not contiguous)
   std::vector<WaveRange> fwd_waves, bwd_waves;
   bool bwd_contiguous = true;
+  // the last forward wave and the first backward wave hold the same layers in the same tiles (every
+  // layer a last level, all narrow, no split): one launch runs both passes' steps on them
+  bool fuse_turn = false;
   std::vector<int32_t> bdd_canon_off; // [m+1] as int32 for the device
   std::vector<int32_t> var_first;     // [n] first storage layer of the variable, -1 if none
   std::vector<int32_t> var_nj;        // [n] |J_i|

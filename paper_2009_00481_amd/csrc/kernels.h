@@ -14,6 +14,8 @@ constexpr int kFwd = 0, kBwd = 1;
 constexpr int kUpdate = 0;    // min-marginals, J_i sum, multiplier update, then step
 constexpr int kNoUpdate = 1;  // step only (initial backward sweep)
 constexpr int kExtract = 2;   // min-marginals to the outputs, then step with unchanged multipliers
+constexpr int kTurn = 3;      // backward launch over the last forward wave's levels: the forward update,
+                              // then the backward update and step (narrow-only, storage-order tiles)
 constexpr int kLbStage = 256; // fixed chunk count of the bound reduction
 constexpr uint32_t kFlat = 7; // gsel code of the node-parallel path for general layers
 

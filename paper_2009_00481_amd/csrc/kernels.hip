@@ -67,11 +67,7 @@ struct Layer {
     m0 = INFINITY;
     m1 = INFINITY;
     if (narrow()) {
-      // arc-marginals (m_fwd + theta) + m_bwd minimised per arc label (eqs. "arc-marginal",
-      // "marginal-aggregation"); a padding node's arcs both lead to BOT
-      const uint32_t lo0 = meta & 3u, hi0 = (meta >> 2) & 3u, lo1 = (meta >> 4) & 3u, hi1 = (meta >> 6) & 3u;
-      m0 = fminf(f.x + c2val(lo0, b), f.y + c2val(lo1, b));
-      m1 = fminf((f.x + lam0) + c2val(hi0, b), (f.y + lam0) + c2val(hi1, b));
+      narrow_marginals(lam0);
     } else if (LOOP) {
       const GRec g = grec_of(D, L);
       for (int u = 0; u < g.w; ++u) {
@@ -81,6 +77,15 @@ struct Layer {
         m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, g.cs, a >> 16));
       }
     }
+  }
+
+  // arc-marginals (m_fwd + theta) + m_bwd minimised per arc label (eqs. "arc-marginal",
+  // "marginal-aggregation") of a narrow layer under multiplier lam; a padding node's arcs both lead
+  // to BOT
+  __device__ __forceinline__ void narrow_marginals(float lam) {
+    const uint32_t lo0 = meta & 3u, hi0 = (meta >> 2) & 3u, lo1 = (meta >> 4) & 3u, hi1 = (meta >> 6) & 3u;
+    m0 = fminf(f.x + c2val(lo0, b), f.y + c2val(lo1, b));
+    m1 = fminf((f.x + lam) + c2val(hi0, b), (f.y + lam) + c2val(hi1, b));
   }
 
   // forward step of the next level (Alg. "Forward BDD update step") pushed from this level: the
@@ -471,31 +476,43 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     }
   }
 
-  const float d = ly.m1 - ly.m0;
+  float d = ly.m1 - ly.m0;
   float lam1 = ly.lam0;
-  if (MODE == kUpdate) {
-    s_d[s] = d;
-    __syncthreads();
+  if (MODE == kUpdate || MODE == kTurn) {
+    static_assert(MODE != kTurn || (DIR == kBwd && NARROW_ONLY && !LIST), "turnaround launch form");
     const int pos = int((ly.meta >> kMetaPosShift) & kMetaField);
     const int len = int((ly.meta >> kMetaLenShift) & kMetaField);
-    if (active && pos == 0) {
-      // J_i sum in ascending row order (the segment is sorted by row)
-      float sum = 0.0f;
-      int nf = 0;
-      for (int q = 0; q < len; ++q) {
-        const float dq = s_d[s + q];
-        if (isinf(dq)) ++nf;
-        else sum += dq;
+    // kTurn: these levels are the last of their rows, so the forward pass's update of them is
+    // followed at once by the backward pass's, with the new multipliers (the forward step below them
+    // has nothing to push; their own forward messages and the terminal children are unchanged)
+#pragma unroll
+    for (int round = 0; round < (MODE == kTurn ? 2 : 1); ++round) {
+      if (round == 1) {
+        ly.narrow_marginals(lam1);
+        d = ly.m1 - ly.m0;
       }
-      s_share[s] = nf ? sum / float(nf) : sum / float(len);
-      s_nf[s] = nf;
+      // the previous round's readers of s_d and s_share are past the barriers that follow
+      s_d[s] = d;
+      __syncthreads();
+      if (active && pos == 0) {
+        // J_i sum in ascending row order (the segment is sorted by row)
+        float sum = 0.0f;
+        int nf = 0;
+        for (int q = 0; q < len; ++q) {
+          const float dq = s_d[s + q];
+          if (isinf(dq)) ++nf;
+          else sum += dq;
+        }
+        s_share[s] = nf ? sum / float(nf) : sum / float(len);
+        s_nf[s] = nf;
+      }
+      __syncthreads();
+      if (active) {
+        const int h = s - pos;
+        lam1 = updated(lam1, d, s_share[h], s_nf[h]);
+      }
     }
-    __syncthreads();
-    if (active) {
-      const int h = s - pos;
-      lam1 = updated(ly.lam0, d, s_share[h], s_nf[h]);
-      D.lam[ly.L] = lam1;
-    }
+    if (active) D.lam[ly.L] = lam1;
   }
   if (MODE == kExtract && active) {
     const int c = D.canon_of[ly.L];
@@ -844,6 +861,11 @@ hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, i
   if (dir == kFwd && mode == kExtract) return wave_dispatch<kFwd, kExtract>(narrow_only, false, nt, tile0, D, s);
   if (dir == kBwd && mode == kUpdate) return wave_dispatch<kBwd, kUpdate>(narrow_only, list, nt, tile0, D, s);
   if (dir == kBwd && mode == kNoUpdate) return wave_dispatch<kBwd, kNoUpdate>(narrow_only, list, nt, tile0, D, s);
+  if (dir == kBwd && mode == kTurn) {
+    if (!narrow_only || list) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((wave_kernel<kBwd, kTurn, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 

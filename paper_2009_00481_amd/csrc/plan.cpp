@@ -855,6 +855,25 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       if (roots) P.bwd_tiles[2 * size_t(t) + 1] = int32_t(uint32_t(P.bwd_tiles[2 * size_t(t) + 1]) | kTileRootBit);
     }
   P.n_lbpart = int64_t(kTile / 64) * int64_t(P.bwd_tiles.size() / 2) + int64_t(P.bwd_big.size() / 2);
+  // turnaround: a variable of the last forward wave is last in each of its rows, so its backward
+  // wave is the first; when the first backward wave holds exactly those layers, tiled alike, the
+  // backward pass's first step on them can follow the forward pass's last one inside one launch
+  P.fuse_turn = false;
+  if (P.Df > 0 && P.Db > 0 && P.n_cuts == 0) {
+    const WaveRange &F = P.fwd_waves.back(), &Bw = P.bwd_waves.front();
+    bool same = F.narrow_only && Bw.narrow_only && !Bw.list && F.big_begin == F.big_end &&
+                Bw.big_begin == Bw.big_end && F.tile_end - F.tile_begin == Bw.tile_end - Bw.tile_begin &&
+                F.tile_end > F.tile_begin;
+    for (int32_t k = 0; same && k < F.tile_end - F.tile_begin; ++k) {
+      const size_t f = 2 * size_t(F.tile_begin + k), b = 2 * size_t(Bw.tile_begin + k);
+      const int64_t f0 = int64_t(uint32_t(P.fwd_tiles[f]) & kTilePosMask), f1 = P.fwd_tiles[f + 1];
+      const int64_t b0 = int64_t(uint32_t(P.bwd_tiles[b]) & kTilePosMask);
+      const int64_t b1 = int64_t(uint32_t(P.bwd_tiles[b + 1]) & ~kTileRootBit);
+      same = f0 == b0 && f1 == b1;
+      for (int64_t L = f0; same && L < f1; ++L) same = P.child[size_t(L)] < 0;
+    }
+    P.fuse_turn = same;
+  }
   // width class of each normal tile in the top bits of its start
   for (int pass = 0; pass < 2; ++pass) {
     auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;

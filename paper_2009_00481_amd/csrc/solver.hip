@@ -82,23 +82,28 @@ struct Timer {
 };
 
 // One pass: every wave in order, one launch per wave (plus one for the wave's big tiles if any).
-int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipStream_t st) {
+// turn (plans with fuse_turn, update mode): the forward pass stops before its last wave and the
+// backward pass's first launch runs that wave's forward update before its own (kTurn).
+int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipStream_t st, bool turn = false) {
   const Plan &P = *S.plan;
   const auto &waves = dir == kFwd ? P.fwd_waves : P.bwd_waves;
+  const size_t nw = waves.size() - ((turn && dir == kFwd) ? 1 : 0);
   Timer tm{ev};
   if (int32_t rc = tm.start(st, dir)) return rc;
-  for (const WaveRange &wr : waves) {
+  for (size_t w = 0; w < nw; ++w) {
+    const WaveRange &wr = waves[w];
     const int nt = wr.tile_end - wr.tile_begin;
     const int nb = wr.big_end - wr.big_begin;
     const bool list = dir == kBwd && wr.list;
+    const int m = (turn && dir == kBwd && w == 0) ? kTurn : mode;
     if (nt > 0)
-      if (int32_t rc = launched(launch_wave(dir, mode, wr.narrow_only, list, nt, wr.tile_begin, S.D, st), "wave kernel"))
+      if (int32_t rc = launched(launch_wave(dir, m, wr.narrow_only, list, nt, wr.tile_begin, S.D, st), "wave kernel"))
         return rc;
     if (nb > 0)
       if (int32_t rc = launched(launch_wave_big(dir, mode, list, nb, wr.big_begin, S.D, st), "wave kernel (big)"))
         return rc;
   }
-  return tm.stop(st, int(waves.size()));
+  return tm.stop(st, int(nw));
 }
 
 // the bound of the backward sweep just run, from its per-tile partials, into the history slot the
@@ -131,9 +136,9 @@ int32_t initial_sweep(Solver &S) {
 // followed by its copy-arc update (Alg. "Parallel min-marginal averaging")
 int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
   const Plan &P = *S.plan;
-  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st)) return rc;
+  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st, P.fuse_turn)) return rc;
   if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), int(P.n_cut_narrow), st), "copy-arc update")) return rc;
-  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st)) return rc;
+  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st, P.fuse_turn)) return rc;
   if (int32_t rc = enqueue_copy_bwd(S, 1, st)) return rc;
   return enqueue_lb(S, ev, st);
 }
@@ -550,9 +555,13 @@ int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
   if (t1) (void)hipEventDestroy(t1);
   if (rc) return rc;
   if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+  // model bytes per pass; with a fused turnaround the last forward wave's share is timed with the
+  // backward pass
   const double pass_bytes = 20.0 * double(P.N) + 8.0 * double(P.I);
-  r.fwd_bytes = pass_bytes * n;
-  r.bwd_bytes = pass_bytes * n;
+  const double turn_bytes =
+      P.fuse_turn ? 20.0 * double(P.fwd_waves.back().nodes) + 8.0 * double(P.fwd_waves.back().layers) : 0.0;
+  r.fwd_bytes = (pass_bytes - turn_bytes) * n;
+  r.bwd_bytes = (pass_bytes + turn_bytes) * n;
   *out = r;
   return BDDMP_OK;
 }

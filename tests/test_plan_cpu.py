@@ -123,6 +123,24 @@ def test_waves_configs():
         _check_waves(ilp, _plan(ilp))
 
 
+def test_turnaround_fusion():
+    """A variable of the last forward wave is last in each of its rows, so it is in the first
+    backward wave; the plan runs the two waves as one launch only when the two sets are equal (and
+    there is no split). Potts grids have this shape, graph matching and split plans do not."""
+    for ilp in [I.config(1), I.config(5), I.graph_matching(300, 300, 10, 3000, seed=1)] + \
+            [I.random_ilp(40, 30, kmax=6, seed=s) for s in range(6)]:
+        pl = _plan(ilp)
+        wf, wb = pl.waves()
+        last_f = set(np.flatnonzero(wf == pl.stats.waves_fwd).tolist())
+        first_b = set(np.flatnonzero(wb == 1).tolist())
+        assert last_f <= first_b
+        if pl.stats.fused_turn:
+            assert last_f == first_b
+    assert _plan(I.config(1)).stats.fused_turn == 1 and _plan(I.config(5)).stats.fused_turn == 1
+    assert _plan(I.graph_matching(300, 300, 10, 3000, seed=1)).stats.fused_turn == 0
+    assert B.Plan(B.Problem.from_ilp(I.config(1)), n_intervals=2).stats.fused_turn == 0
+
+
 def test_greedy_colour_order_matches_generator():
     ilp = I.graph_matching(200, 200, 10, 2000, seed=3)
     prob = B.Problem.from_ilp(ilp, order=False)

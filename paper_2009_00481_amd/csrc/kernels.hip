@@ -573,10 +573,12 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     if constexpr (!NARROW_ONLY)
       if (gen && (ly.meta & kMetaRootBit)) e = double(s_g.e[myk]);
     // bound partial per wavefront: a fixed-shape wavefront sum, only in tiles holding root levels
-    // (the branch is uniform over the workgroup)
-    double v = 0.0;
-    if (roots) v = wave_sum(e);
-    if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
+    // (the branch is uniform over the workgroup); the partials of other tiles stay at the zero the
+    // solver's reset stored
+    if (roots) {
+      const double v = wave_sum(e);
+      if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
+    }
   }
 }
 
@@ -669,18 +671,27 @@ __global__ __launch_bounds__(256) void lb_stage_kernel(const Dev D, int nparts) 
   __shared__ double sh[4];
   const int chunk = (nparts + kLbStage - 1) / kLbStage;
   const int q0 = int(blockIdx.x) * chunk, q1 = min(nparts, q0 + chunk);
-  double acc = 0.0;
-  for (int q = q0 + int(threadIdx.x); q < q1; q += 256) acc += D.lbpart[q];
-  const double s = block_sum(acc, sh);
+  // four independent running sums per lane (loads in flight together), then combined in order
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int q = q0 + int(threadIdx.x);
+  for (; q + 3 * 256 < q1; q += 4 * 256) {
+    a0 += D.lbpart[q];
+    a1 += D.lbpart[q + 256];
+    a2 += D.lbpart[q + 2 * 256];
+    a3 += D.lbpart[q + 3 * 256];
+  }
+  for (; q < q1; q += 256) a0 += D.lbpart[q];
+  const double s = block_sum((a0 + a1) + (a2 + a3), sh);
   if (threadIdx.x == 0) D.part[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(kLbStage) void lb_final_kernel(const Dev D, int which) {
   __shared__ double sh[kLbStage / 64];
+  const long long n = *D.hist_n;
+  const double c = D.lbc[which];
   const double s = block_sum(D.part[threadIdx.x], sh);
   if (threadIdx.x == 0) {
-    const long long n = *D.hist_n;
-    D.lb_hist[n % D.hist_cap] = s + D.lbc[which];
+    D.lb_hist[n % D.hist_cap] = s + c;
     *D.hist_n = n + 1;
   }
 }

@@ -204,9 +204,10 @@ __global__ __launch_bounds__(kTile) void smooth_wave_kernel(const Dev D, const S
       }
     }
     const double e = (active && (meta & kMetaRootBit)) ? double(r) : 0.0;
-    double v = 0.0;
-    if (roots) v = wave_sum(e);
-    if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
+    if (roots) {
+      const double v = wave_sum(e);
+      if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
+    }
   }
 }
 

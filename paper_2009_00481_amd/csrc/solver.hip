@@ -309,6 +309,9 @@ int32_t solver_reset(Solver &S) {
   if (int32_t rc = launched(launch_init_lambda(S.D, int(P.I), S.stream), "init_lambda")) return rc;
   if (int32_t rc = launched(launch_root_zero(S.D, P.m, S.stream), "root_zero")) return rc;
   if (int32_t rc = launched(launch_copy_init(S.D, int(P.n_cuts), S.stream), "copy_init")) return rc;
+  // bound partials: tiles without a root level never write theirs, which stay zero
+  const int nlb = int(2 * (P.n_lbpart + P.n_cut_parts + 1));
+  if (int32_t rc = launched(launch_fill(reinterpret_cast<float *>(S.D.lbpart), 0.0f, nlb, S.stream), "fill")) return rc;
   if (int32_t rc = launched(launch_set_counter(S.D, S.n_hist, S.stream), "set_counter")) return rc;
   if (int32_t rc = launched(launch_free_const(S.D, P.n, 1.0f, S.stream), "free_const")) return rc;
   S.iters = 0;

@@ -93,6 +93,9 @@ typedef struct {
   int64_t n_copy_pairs;         /* copy-arc pairs (live arcs leaving the cut levels)       */
   int32_t fused_turn;           /* 1 if the last forward wave and the first backward wave run
                                    as one launch (their levels are the rows' last levels)  */
+  int32_t fused_wrap;           /* 1 if, inside a run of iterations, the last backward wave
+                                   and the next iteration's first forward wave run as one
+                                   launch (their levels are the rows' roots)                */
 } bddmp_stats;
 
 typedef struct {

@@ -42,7 +42,7 @@ class Stats(C.Structure):
                 ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
                 ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32),
                 ("n_intervals", C.c_int32), ("n_cuts", C.c_int64), ("n_copy_pairs", C.c_int64),
-                ("fused_turn", C.c_int32)]
+                ("fused_turn", C.c_int32), ("fused_wrap", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -230,6 +230,7 @@ int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   out->n_cuts = P.n_cuts;
   out->n_copy_pairs = P.n_copy;
   out->fused_turn = P.fuse_turn ? 1 : 0;
+  out->fused_wrap = P.fuse_wrap ? 1 : 0;
   return BDDMP_OK;
 }
 

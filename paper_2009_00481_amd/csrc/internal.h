@@ -140,6 +140,10 @@ struct Plan {
   // the last forward wave and the first backward wave hold the same layers in the same tiles (every
   // layer a last level, all narrow, no split): one launch runs both passes' steps on them
   bool fuse_turn = false;
+  // wrap-around: the first forward wave and the last backward wave hold the same levels in the same
+  // tiles (every layer a root level, all narrow, no split): inside a run of iterations, one launch
+  // runs the last backward step of one iteration and the first forward step of the next
+  bool fuse_wrap = false;
   std::vector<int32_t> bdd_canon_off; // [m+1] as int32 for the device
   std::vector<int32_t> var_first;     // [n] first storage layer of the variable, -1 if none
   std::vector<int32_t> var_nj;        // [n] |J_i|

@@ -16,6 +16,9 @@ constexpr int kNoUpdate = 1;  // step only (initial backward sweep)
 constexpr int kExtract = 2;   // min-marginals to the outputs, then step with unchanged multipliers
 constexpr int kTurn = 3;      // backward launch over the last forward wave's levels: the forward update,
                               // then the backward update and step (narrow-only, storage-order tiles)
+constexpr int kWrap = 4;      // forward launch over the first forward wave's levels (the rows' roots): the
+                              // last backward wave's update and bound partials, then the next
+                              // iteration's forward update and step
 constexpr int kLbStage = 256; // fixed chunk count of the bound reduction
 constexpr uint32_t kFlat = 7; // gsel code of the node-parallel path for general layers
 
@@ -64,8 +67,9 @@ struct Dev {
 
 // One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).
 // narrow_only selects the variant without wide levels, list the backward index-list variant.
+// kWrap (dir kFwd, narrow-only, no list): bwd_tile0 is the first backward tile of the same levels.
 hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, int tile0, const Dev &D,
-                       hipStream_t s);
+                       hipStream_t s, int bwd_tile0 = 0);
 // Big tiles (one variable with more than kTile rows each) of one wave.
 hipError_t launch_wave_big(int dir, int mode, bool list, int nb, int big0, const Dev &D, hipStream_t s);
 

@@ -115,6 +115,13 @@ struct Layer {
     }
   }
 
+  // a narrow root level's new backward message (the backward step's value at node 0) as a bound
+  // term, 0 on other levels
+  __device__ __forceinline__ double root_value(float lam1) const {
+    const float n0 = fminf(c2val(meta & 3u, b), c2val((meta >> 2) & 3u, b) + lam1);
+    return (meta & kMetaRootBit) ? double(n0) : 0.0;
+  }
+
   // backward step of this level (Alg. "Backward BDD update step") with the updated multiplier,
   // stored at the parent layer's child slots; returns the root's new backward message (E^j) on a
   // root level, else 0
@@ -272,7 +279,7 @@ __device__ __forceinline__ float staged(const float *cb, int c0, uint32_t c) {
 // collected per tile and run either node-parallel over the whole tile (flat path) or by groups of
 // G lanes, as the tile's width class selects.
 template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
-__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0) {
+__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0, const int bwd_tile0) {
   __shared__ float s_d[kTile];
   __shared__ int s_wcnt[kTile / 64];
   // LDS of the general-layer paths (one element in narrow-only instantiations)
@@ -302,7 +309,10 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   const int p0 = int(w0 & kTilePosMask);
   // a backward tile's end carries bit 31 when the tile holds a root level
   const uint32_t end = uint32_t(tiles[2 * tix + 1]);
-  const bool roots = DIR == kBwd && (end & kTileRootBit) != 0u;
+  // kWrap: the same levels' backward tile (its root flag and bound partials)
+  const int btix = MODE == kWrap ? bwd_tile0 + (tix - tile0) : tix;
+  const bool roots = (DIR == kBwd && (end & kTileRootBit) != 0u) ||
+                     (MODE == kWrap && (uint32_t(D.bwd_tiles[2 * btix + 1]) & kTileRootBit) != 0u);
   const int cnt = int(end & ~kTileRootBit) - p0;
   const int s = int(threadIdx.x);
   const bool active = s < cnt;
@@ -478,15 +488,19 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
 
   float d = ly.m1 - ly.m0;
   float lam1 = ly.lam0;
-  if (MODE == kUpdate || MODE == kTurn) {
+  if (MODE == kUpdate || MODE == kTurn || MODE == kWrap) {
     static_assert(MODE != kTurn || (DIR == kBwd && NARROW_ONLY && !LIST), "turnaround launch form");
+    static_assert(MODE != kWrap || (DIR == kFwd && NARROW_ONLY && !LIST), "wrap-around launch form");
     const int pos = int((ly.meta >> kMetaPosShift) & kMetaField);
     const int len = int((ly.meta >> kMetaLenShift) & kMetaField);
     // kTurn: these levels are the last of their rows, so the forward pass's update of them is
     // followed at once by the backward pass's, with the new multipliers (the forward step below them
-    // has nothing to push; their own forward messages and the terminal children are unchanged)
+    // has nothing to push; their own forward messages and the terminal children are unchanged).
+    // kWrap: these levels are the roots of their rows; the backward pass's update of them (its last
+    // wave) is followed by the next iteration's forward update (nothing is stored between the two:
+    // a root has no parent level, and its forward message and children stay as they are).
 #pragma unroll
-    for (int round = 0; round < (MODE == kTurn ? 2 : 1); ++round) {
+    for (int round = 0; round < (MODE == kTurn || MODE == kWrap ? 2 : 1); ++round) {
       if (round == 1) {
         ly.narrow_marginals(lam1);
         d = ly.m1 - ly.m0;
@@ -510,6 +524,14 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
       if (active) {
         const int h = s - pos;
         lam1 = updated(lam1, d, s_share[h], s_nf[h]);
+      }
+      if constexpr (MODE == kWrap) {
+        if (round == 0 && roots) {
+          // the backward step at the roots with the updated multipliers: E^j of each row, summed per
+          // wavefront into the backward tile's bound partials
+          const double v = wave_sum(active ? ly.root_value(lam1) : 0.0);
+          if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * btix + (int(threadIdx.x) >> 6)] = v;
+        }
       }
     }
     if (active) D.lam[ly.L] = lam1;
@@ -856,25 +878,30 @@ int blocks_for(int64_t count, int per) { return int((count + per - 1) / per); }
 template <int DIR, int MODE>
 static hipError_t wave_dispatch(bool narrow_only, bool list, int nt, int tile0, const Dev &D, hipStream_t s) {
   if (narrow_only && !list)
-    hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0, 0);
   else if (narrow_only)
-    hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, true>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    hipLaunchKernelGGL((wave_kernel<DIR, MODE, true, true>), dim3(nt), dim3(kTile), 0, s, D, tile0, 0);
   else if (!list)
-    hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, false>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, false>), dim3(nt), dim3(kTile), 0, s, D, tile0, 0);
   else
-    hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, true>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    hipLaunchKernelGGL((wave_kernel<DIR, MODE, false, true>), dim3(nt), dim3(kTile), 0, s, D, tile0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, int tile0, const Dev &D,
-                       hipStream_t s) {
+                       hipStream_t s, int bwd_tile0) {
   if (dir == kFwd && mode == kUpdate) return wave_dispatch<kFwd, kUpdate>(narrow_only, false, nt, tile0, D, s);
   if (dir == kFwd && mode == kExtract) return wave_dispatch<kFwd, kExtract>(narrow_only, false, nt, tile0, D, s);
   if (dir == kBwd && mode == kUpdate) return wave_dispatch<kBwd, kUpdate>(narrow_only, list, nt, tile0, D, s);
   if (dir == kBwd && mode == kNoUpdate) return wave_dispatch<kBwd, kNoUpdate>(narrow_only, list, nt, tile0, D, s);
   if (dir == kBwd && mode == kTurn) {
     if (!narrow_only || list) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((wave_kernel<kBwd, kTurn, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0);
+    hipLaunchKernelGGL((wave_kernel<kBwd, kTurn, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0, 0);
+    return hipGetLastError();
+  }
+  if (dir == kFwd && mode == kWrap) {
+    if (!narrow_only || list) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((wave_kernel<kFwd, kWrap, true, false>), dim3(nt), dim3(kTile), 0, s, D, tile0, bwd_tile0);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

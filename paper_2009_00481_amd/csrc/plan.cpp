@@ -874,6 +874,25 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     }
     P.fuse_turn = same;
   }
+  // wrap-around: a variable of the first forward wave is first in each of its rows, so its backward
+  // wave is the last; when that wave holds exactly those layers, tiled alike, the last backward step
+  // of one iteration and the first forward step of the next can share a launch
+  P.fuse_wrap = false;
+  if (P.Df > 1 && P.Db > 1 && P.n_cuts == 0) {
+    const WaveRange &F = P.fwd_waves.front(), &Bw = P.bwd_waves.back();
+    bool same = F.narrow_only && Bw.narrow_only && !Bw.list && F.big_begin == F.big_end &&
+                Bw.big_begin == Bw.big_end && F.tile_end - F.tile_begin == Bw.tile_end - Bw.tile_begin &&
+                F.tile_end > F.tile_begin;
+    for (int32_t k = 0; same && k < F.tile_end - F.tile_begin; ++k) {
+      const size_t f = 2 * size_t(F.tile_begin + k), b = 2 * size_t(Bw.tile_begin + k);
+      const int64_t f0 = int64_t(uint32_t(P.fwd_tiles[f]) & kTilePosMask), f1 = P.fwd_tiles[f + 1];
+      const int64_t b0 = int64_t(uint32_t(P.bwd_tiles[b]) & kTilePosMask);
+      const int64_t b1 = int64_t(uint32_t(P.bwd_tiles[b + 1]) & ~kTileRootBit);
+      same = f0 == b0 && f1 == b1;
+      for (int64_t L = f0; same && L < f1; ++L) same = P.parent[size_t(L)] < 0;
+    }
+    P.fuse_wrap = same;
+  }
   // width class of each normal tile in the top bits of its start
   for (int pass = 0; pass < 2; ++pass) {
     auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;

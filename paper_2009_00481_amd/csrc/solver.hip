@@ -27,13 +27,18 @@ struct Solver {
   int64_t iters = 0;
   // one update iteration captured as a HIP graph and replayed by iterate (the kernel arguments,
   // including the group selection, are baked in: a change of D.gsel re-captures)
+  // With a wrap-around plan a run of n iterations is the first forward wave, n - 1 replays of
+  // gexec_wrap (which ends with the wrap-around launch: the last backward wave and the next
+  // iteration's first forward wave) and one replay of gexec (which ends with the plain last backward
+  // wave), so that the state between calls is always that after whole iterations.
   bool use_graph = true;
   hipStream_t cap = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr, gexec_wrap = nullptr;
   uint32_t graph_gsel = 0;
   bool costs_replaced = false;  // bddmp_solver_set_costs was called (instance constants are stale)
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gexec_wrap) (void)hipGraphExecDestroy(gexec_wrap);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -84,17 +89,30 @@ struct Timer {
 // One pass: every wave in order, one launch per wave (plus one for the wave's big tiles if any).
 // turn (plans with fuse_turn, update mode): the forward pass stops before its last wave and the
 // backward pass's first launch runs that wave's forward update before its own (kTurn).
-int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipStream_t st, bool turn = false) {
+// skip_first: the forward pass starts at its second wave (the first ran already); wrap: the backward
+// pass's last wave is the wrap-around launch (kWrap), which also runs the next iteration's first
+// forward wave.
+int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipStream_t st, bool turn = false,
+                 bool skip_first = false, bool wrap = false) {
   const Plan &P = *S.plan;
   const auto &waves = dir == kFwd ? P.fwd_waves : P.bwd_waves;
   const size_t nw = waves.size() - ((turn && dir == kFwd) ? 1 : 0);
+  const size_t w0 = (skip_first && dir == kFwd) ? 1 : 0;
   Timer tm{ev};
   if (int32_t rc = tm.start(st, dir)) return rc;
-  for (size_t w = 0; w < nw; ++w) {
+  for (size_t w = w0; w < nw; ++w) {
     const WaveRange &wr = waves[w];
     const int nt = wr.tile_end - wr.tile_begin;
     const int nb = wr.big_end - wr.big_begin;
     const bool list = dir == kBwd && wr.list;
+    if (wrap && dir == kBwd && w + 1 == nw) {
+      // same tiles as the first forward wave (the plan checked it), launched in forward numbering
+      const WaveRange &f = P.fwd_waves.front();
+      if (int32_t rc = launched(launch_wave(kFwd, kWrap, true, false, nt, f.tile_begin, S.D, st, wr.tile_begin),
+                                "wave kernel (wrap-around)"))
+        return rc;
+      continue;
+    }
     const int m = (turn && dir == kBwd && w == 0) ? kTurn : mode;
     if (nt > 0)
       if (int32_t rc = launched(launch_wave(dir, m, wr.narrow_only, list, nt, wr.tile_begin, S.D, st), "wave kernel"))
@@ -103,7 +121,7 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
       if (int32_t rc = launched(launch_wave_big(dir, mode, list, nb, wr.big_begin, S.D, st), "wave kernel (big)"))
         return rc;
   }
-  return tm.stop(st, int(nw));
+  return tm.stop(st, int(nw - w0));
 }
 
 // the bound of the backward sweep just run, from its per-tile partials, into the history slot the
@@ -133,12 +151,14 @@ int32_t initial_sweep(Solver &S) {
 }
 
 // enqueue one iteration (forward pass, backward pass, bound) on st; with a split each pass is
-// followed by its copy-arc update (Alg. "Parallel min-marginal averaging")
-int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st) {
+// followed by its copy-arc update (Alg. "Parallel min-marginal averaging"). form 0: a whole
+// iteration; with a wrap-around plan, form 1 starts at the second forward wave and ends with the
+// wrap-around launch, form 2 starts at the second forward wave and ends with the plain last wave.
+int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st, int form = 0) {
   const Plan &P = *S.plan;
-  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st, P.fuse_turn)) return rc;
+  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st, P.fuse_turn, form != 0)) return rc;
   if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), int(P.n_cut_narrow), st), "copy-arc update")) return rc;
-  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st, P.fuse_turn)) return rc;
+  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st, P.fuse_turn, false, form == 1)) return rc;
   if (int32_t rc = enqueue_copy_bwd(S, 1, st)) return rc;
   return enqueue_lb(S, ev, st);
 }
@@ -152,15 +172,16 @@ int32_t one_iteration(Solver &S, std::vector<EventPair> *ev) {
 
 void drop_graph(Solver &S) {
   if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
+  if (S.gexec_wrap) (void)hipGraphExecDestroy(S.gexec_wrap);
   S.gexec = nullptr;
+  S.gexec_wrap = nullptr;
 }
 
-// Captures one iteration's launches on a private stream into an executable graph.
-int32_t capture_iteration(Solver &S) {
-  drop_graph(S);
+// Captures one iteration's launches (in the given form) on a private stream into an executable graph.
+int32_t capture_form(Solver &S, int form, hipGraphExec_t &out) {
   if (!S.cap) HIP_TRY(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
   HIP_TRY(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  const int32_t rc = enqueue_iteration(S, nullptr, S.cap);
+  const int32_t rc = enqueue_iteration(S, nullptr, S.cap, form);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(S.cap, &g);
   if (rc) {
@@ -168,12 +189,26 @@ int32_t capture_iteration(Solver &S) {
     return rc;
   }
   if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
-  const hipError_t ei = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0);
+  const hipError_t ei = hipGraphInstantiate(&out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) {
-    S.gexec = nullptr;
+    out = nullptr;
     return hip_fail(ei, "hipGraphInstantiate");
   }
+  return BDDMP_OK;
+}
+
+// The graphs iterate replays: one whole iteration, or with a wrap-around plan the two forms of
+// enqueue_iteration that runs of iterations are made of.
+int32_t capture_iteration(Solver &S) {
+  drop_graph(S);
+  const bool wrap = S.plan->fuse_wrap;
+  if (int32_t rc = capture_form(S, wrap ? 2 : 0, S.gexec)) return rc;
+  if (wrap)
+    if (int32_t rc = capture_form(S, 1, S.gexec_wrap)) {
+      drop_graph(S);
+      return rc;
+    }
   S.graph_gsel = S.D.gsel;
   return BDDMP_OK;
 }
@@ -321,10 +356,20 @@ int32_t solver_reset(Solver &S) {
 int32_t solver_iterate(Solver &S, int32_t n) {
   if (n < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
   if (S.use_graph && n > 0) {
-    if (!S.gexec || S.graph_gsel != S.D.gsel)
+    const Plan &P = *S.plan;
+    if (!S.gexec || (P.fuse_wrap && !S.gexec_wrap) || S.graph_gsel != S.D.gsel)
       if (int32_t rc = capture_iteration(S)) return rc;
+    if (P.fuse_wrap) {
+      // the first forward wave, then n - 1 iterations that end one wave into the next, then one
+      // that ends with the plain last backward wave
+      const WaveRange &f = P.fwd_waves.front();
+      if (int32_t rc = launched(launch_wave(kFwd, kUpdate, true, false, f.tile_end - f.tile_begin, f.tile_begin, S.D,
+                                            S.stream),
+                                "wave kernel"))
+        return rc;
+    }
     for (int32_t t = 0; t < n; ++t) {
-      HIP_TRY(hipGraphLaunch(S.gexec, S.stream), "hipGraphLaunch");
+      HIP_TRY(hipGraphLaunch((P.fuse_wrap && t + 1 < n) ? S.gexec_wrap : S.gexec, S.stream), "hipGraphLaunch");
       S.n_hist++;
       S.iters++;
     }

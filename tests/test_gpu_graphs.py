@@ -35,6 +35,8 @@ def _trace(ilp, graphs: bool, switch_groups: bool = False):
 def test_graph_replay_equals_host_launches(name):
     if name == "cfg1":
         ilp = I.config(1)
+        # runs of iterations here use the wrap-around launch; host launches never do
+        assert B.Plan(B.Problem.from_ilp(ilp)).stats.fused_wrap == 1
     elif name == "tomo":
         ilp = I.tomography(14, seed=1, unary="normal")
     else:

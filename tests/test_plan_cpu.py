@@ -136,9 +136,20 @@ def test_turnaround_fusion():
         assert last_f <= first_b
         if pl.stats.fused_turn:
             assert last_f == first_b
-    assert _plan(I.config(1)).stats.fused_turn == 1 and _plan(I.config(5)).stats.fused_turn == 1
-    assert _plan(I.graph_matching(300, 300, 10, 3000, seed=1)).stats.fused_turn == 0
-    assert B.Plan(B.Problem.from_ilp(I.config(1)), n_intervals=2).stats.fused_turn == 0
+        # mirror image: a variable of the first forward wave is first in its rows, so in the last
+        # backward wave; the wrap-around launch needs the two sets equal
+        first_f = set(np.flatnonzero(wf == 1).tolist())
+        last_b = set(np.flatnonzero(wb == pl.stats.waves_bwd).tolist())
+        assert last_b <= first_f or pl.stats.waves_bwd == 0
+        if pl.stats.fused_wrap:
+            assert first_f == last_b and pl.stats.waves_fwd > 1
+    for c in (1, 5):
+        st = _plan(I.config(c)).stats
+        assert st.fused_turn == 1 and st.fused_wrap == 1
+    st = _plan(I.graph_matching(300, 300, 10, 3000, seed=1)).stats
+    assert st.fused_turn == 0 and st.fused_wrap == 0
+    st = B.Plan(B.Problem.from_ilp(I.config(1)), n_intervals=2).stats
+    assert st.fused_turn == 0 and st.fused_wrap == 0
 
 
 def test_greedy_colour_order_matches_generator():

@@ -345,8 +345,11 @@ int32_t bddmp_solver_set_costs(bddmp_solver *s, const double *cost_dev);
  * Launch mode of bddmp_solver_iterate. enable = 1 (default): one iteration (every wave launch of
  * both passes and the bound reduction) is captured once as a HIP graph on a private stream and
  * replayed on the solver's stream, one graph launch per iteration; the bound's history slot comes
- * from a device counter, so replays need no changed arguments. enable = 0: every wave is launched
- * from the host. Both give bitwise the same results.
+ * from a device counter, so replays need no changed arguments. With bddmp_stats.fused_wrap = 1 a call
+ * of n iterations launches the first forward wave, then replays n - 1 times an iteration that ends
+ * with the launch that also runs the next iteration's first forward wave, and once an iteration that
+ * ends with the plain last backward wave: between calls the state is always that after whole
+ * iterations. enable = 0: every wave is launched from the host. Both give bitwise the same results.
  */
 int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
 

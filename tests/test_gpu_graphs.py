@@ -69,3 +69,32 @@ def test_history_ring_wraps_with_graphs():
     ref = t.lb_history(64)
     torch.cuda.synchronize()
     assert np.array_equal(h, ref[-8:])
+
+
+def test_full_size_replays_equal_host_launches():
+    """The benchmark's Potts 256x256x8 workload as bench.py runs it (graph replays, so the
+    wrap-around launch inside each run of iterations) against host launches: bitwise equal
+    multipliers, bounds and fresh min-marginals after two runs of 10 iterations."""
+    import torch
+
+    ilp = I.config(2)
+    plan = B.Plan(B.Problem.from_ilp(ilp), hist_cap=64)
+    assert plan.stats.fused_turn == 1 and plan.stats.fused_wrap == 1
+    out = []
+    for graphs in (False, True):
+        print(f"[graphs] cfg2 graphs={graphs}", flush=True)
+        s = B.Solver(plan)
+        s.set_graphs(graphs)
+        s.iterate(10)
+        s.iterate(10)
+        lam = s.get_lambda().cpu().numpy()
+        m0, m1 = s.min_marginals()
+        hist = s.lb_history(64)
+        torch.cuda.synchronize()
+        out.append((lam, hist, m0.cpu().numpy(), m1.cpu().numpy()))
+        del s
+        torch.cuda.empty_cache()
+    a, b = out
+    assert a[1].shape == (21,)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

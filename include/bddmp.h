@@ -27,7 +27,8 @@
  *     device memory and never frees the arena.
  *   - Device work is enqueued on the caller's HIP stream. Only the calls that
  *     hand back host values (lower_bound, lb_history, round_primal,
- *     time_kernels) synchronise that stream.
+ *     time_kernels) and the calls that check device inputs for NaN and
+ *     infinities (set_lambda, set_copy_duals, set_costs) synchronise it.
  *   - One handle is used by one host thread at a time.
  *   - Per-incidence arrays use the canonical incidence order: rows in input
  *     order, and within a row its variables in processing order (the levels
@@ -49,11 +50,11 @@ extern "C" {
 #define BDDMP_INVALID_ARG (-1)    /* bad pointer, size, index, sense or permutation          */
 #define BDDMP_ROW_INFEASIBLE (-2) /* a row has no 0/1 solution (its BDD would be empty)      */
 #define BDDMP_BDD_TOO_LARGE (-3)  /* node budget exceeded, or a level wider than 32767       */
-#define BDDMP_NOT_INTEGER (-4)    /* reserved: coefficients arrive as integers               */
+#define BDDMP_NOT_INTEGER (-4)    /* a real coefficient or right-hand side is not an integer  */
 #define BDDMP_CONFLICT (-5)       /* rows force one variable to both 0 and 1                 */
 #define BDDMP_DEVICE (-6)         /* a HIP call failed; the message holds HIP's error string */
 #define BDDMP_BAD_STATE (-7)      /* call out of order                                       */
-#define BDDMP_NONFINITE (-8)      /* NaN or infinite multiplier or bound                     */
+#define BDDMP_NONFINITE (-8)      /* NaN or infinite cost, multiplier, copy dual or bound    */
 
 /* row senses */
 #define BDDMP_EQ 0
@@ -68,8 +69,6 @@ typedef struct {
   int32_t order_mode;     /* 0: the problem's order (identity if none set); 1: greedy colouring */
   int32_t hist_cap;       /* bound history ring length on the device (default 4096)           */
   int64_t node_budget;    /* max total BDD nodes, 0 = unlimited                                */
-  double stop_rel_impr;   /* reserved: the stop rule is bddmp_solver_iterate_until's argument    */
-  float alpha;            /* reserved for the smoothed variant, 0 = min-plus                    */
   int32_t tile_work;      /* a tile closes once its general levels hold this many own plus next-
                              level nodes (0: 2048; the node-parallel path stages up to 2048 of each) */
   const char *tiling;     /* general-layer path by width class, "g0,g1,g2,g3" (NULL: default
@@ -116,7 +115,7 @@ int32_t bddmp_options_default(bddmp_options *opt);
 
 /*
  * A problem with n_vars binary variables and objective c (Sec. 3, eq. "binary-program").
- * cost: host array [n_vars], copied. n_vars >= 0.
+ * cost: host array [n_vars], copied. n_vars >= 0. NONFINITE if a cost is NaN or infinite.
  */
 int32_t bddmp_problem_create(int32_t n_vars, const double *cost, bddmp_problem **out);
 
@@ -126,9 +125,21 @@ int32_t bddmp_problem_create(int32_t n_vars, const double *cost, bddmp_problem *
  * Each row becomes one subproblem X_j with I_j = {i : a_ji != 0} (Sec. 3, Example "ILP");
  * zero coefficients are dropped. A column repeated inside a row is INVALID_ARG.
  * sense: BDDMP_EQ, BDDMP_LE or BDDMP_GE. All arrays are host memory and copied.
+ * The diagrams are built from partial sums of the coefficients in int64: a row whose
+ * sum_q |coef[q]| + |rhs| reaches 2^62 is INVALID_ARG (nothing of the call is kept).
  */
 int32_t bddmp_problem_add_rows(bddmp_problem *p, int32_t n_rows, const int64_t *row_ptr, const int32_t *col,
                                const int64_t *coef, const int8_t *sense, const int64_t *rhs);
+
+/*
+ * bddmp_problem_add_rows for coefficients and right-hand sides held as doubles (as LP and MPS
+ * readers deliver them). The method takes integer rows (Sec. 3, Example "ILP"; the threshold
+ * construction of Sec. 5.2 works on integer partial sums): every coef[q] and rhs[r] must be a
+ * finite integral value of magnitude below 2^53, else NOT_INTEGER and nothing of the call is kept.
+ * Other arguments and errors as bddmp_problem_add_rows.
+ */
+int32_t bddmp_problem_add_rows_real(bddmp_problem *p, int32_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                                    const double *coef, const int8_t *sense, const double *rhs);
 
 /*
  * Processing order of Alg. "Min-marginal averaging": perm[r] is the variable processed r-th by
@@ -252,7 +263,9 @@ int32_t bddmp_solver_iterate_until(bddmp_solver *s, int32_t max_iters, double mi
 /*
  * Latest bound, dual-feasibility residual max_i |c_i - sum_j lambda^j_i| and the bound valid
  * for any lambda, LB + sum_i min(0, c_i - sum_j lambda^j_i) (App. A.1). Synchronises the stream.
- * Any output pointer may be NULL. NONFINITE if the bound is NaN.
+ * Any output pointer may be NULL. NONFINITE if the bound is NaN or infinite (the outputs still
+ * receive the values); finite multipliers can give an infinite bound when a row's minimum
+ * overflows fp32.
  */
 int32_t bddmp_solver_lower_bound(bddmp_solver *s, double *lb, double *residual, double *any_lambda_bound);
 
@@ -281,7 +294,9 @@ int32_t bddmp_solver_min_marginals(bddmp_solver *s, float *m0_dev, float *m1_dev
 int32_t bddmp_solver_get_lambda(bddmp_solver *s, float *lam_dev);
 
 /* Replaces the multipliers from lam_dev (device, canonical order) and re-runs the initial
- * backward sweep (resume from a checkpoint); appends the new bound. Asynchronous. */
+ * backward sweep (resume from a checkpoint); appends the new bound. The values are checked on the
+ * device first and the stream synchronised: NONFINITE if any is NaN or infinite, and then the
+ * solver's state is unchanged. */
 int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
 
 /*
@@ -293,7 +308,9 @@ int32_t bddmp_solver_set_lambda(bddmp_solver *s, const float *lam_dev);
  * dbw: the last forward / backward updates delta (the next update of the other dual uses them).
  * get: any pointer may be NULL (device arrays). Asynchronous.
  * set: all four required; then the initial backward sweep re-runs (as bddmp_solver_set_lambda),
- * appending a bound. Together with lambda this is a complete checkpoint of a split solver.
+ * appending a bound; NONFINITE (state unchanged) if any value is NaN or infinite, checked on the
+ * device after which the stream is synchronised. Together with lambda this is a complete
+ * checkpoint of a split solver.
  */
 int32_t bddmp_solver_get_copy_duals(bddmp_solver *s, float *mu_bar_dev, float *mu_dev, float *dfw_dev, float *dbw_dev);
 int32_t bddmp_solver_set_copy_duals(bddmp_solver *s, const float *mu_bar_dev, const float *mu_dev, const float *dfw_dev,
@@ -337,7 +354,8 @@ int32_t bddmp_solver_smooth_grad(bddmp_solver *s, float alpha, int32_t n_iters, 
 /*
  * Replaces the costs c (device double [n_vars]) used by bddmp_solver_reset and the smoothed run
  * (lambda = c / |J_i| and the terms of variables in no row). The plan keeps its own costs: after
- * this call bddmp_solver_instance_bounds returns BAD_STATE. Asynchronous.
+ * this call bddmp_solver_instance_bounds returns BAD_STATE. The values are checked on the device
+ * and the stream synchronised: NONFINITE (costs unchanged) if any is NaN or infinite.
  */
 int32_t bddmp_solver_set_costs(bddmp_solver *s, const double *cost_dev);
 

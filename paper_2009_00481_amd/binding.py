@@ -31,8 +31,8 @@ class BddmpError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("order_mode", C.c_int32), ("hist_cap", C.c_int32), ("node_budget", C.c_int64),
-                ("stop_rel_impr", C.c_double), ("alpha", C.c_float), ("tile_work", C.c_int32),
-                ("tiling", C.c_char_p), ("n_intervals", C.c_int32), ("split_gamma", C.c_float)]
+                ("tile_work", C.c_int32), ("tiling", C.c_char_p), ("n_intervals", C.c_int32),
+                ("split_gamma", C.c_float)]
 
 
 class Stats(C.Structure):
@@ -65,6 +65,7 @@ SIGNATURES = {
     "bddmp_options_default": (_I32, [C.POINTER(Options)]),
     "bddmp_problem_create": (_I32, [_I32, _P, C.POINTER(_P)]),
     "bddmp_problem_add_rows": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
+    "bddmp_problem_add_rows_real": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
     "bddmp_problem_set_order": (_I32, [_P, _P]),
     "bddmp_plan_create": (_I32, [_P, C.POINTER(Options), C.POINTER(_P)]),
     "bddmp_plan_create_batch": (_I32, [_P, _I32, C.POINTER(Options), C.POINTER(_P)]),
@@ -171,6 +172,17 @@ def bddmp_problem_add_rows(h, row_ptr, col, coef, sense, rhs):
     n_rows = int(row_ptr.shape[0] - 1)
     _check(lib().bddmp_problem_add_rows(h, n_rows, _ptr(row_ptr), _ptr(col) if col.size else None,
                                         _ptr(coef) if coef.size else None, _ptr(sense), _ptr(rhs)))
+
+
+def bddmp_problem_add_rows_real(h, row_ptr, col, coef, sense, rhs):
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    coef = np.ascontiguousarray(coef, np.float64)
+    sense = np.ascontiguousarray(sense, np.int8)
+    rhs = np.ascontiguousarray(rhs, np.float64)
+    n_rows = int(row_ptr.shape[0] - 1)
+    _check(lib().bddmp_problem_add_rows_real(h, n_rows, _ptr(row_ptr), _ptr(col) if col.size else None,
+                                             _ptr(coef) if coef.size else None, _ptr(sense), _ptr(rhs)))
 
 
 def bddmp_problem_set_order(h, perm):

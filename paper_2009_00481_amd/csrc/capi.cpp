@@ -1,4 +1,5 @@
 // C-ABI of bddmp: argument checks, handle ownership, status codes and the last-error message.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -66,6 +67,8 @@ int32_t bddmp_problem_create(int32_t n_vars, const double *cost, bddmp_problem *
     if (!out) return set_error(BDDMP_INVALID_ARG, "null out");
     *out = nullptr;
     if (n_vars < 0 || (n_vars > 0 && !cost)) return set_error(BDDMP_INVALID_ARG, "bad n_vars or null cost");
+    for (int32_t i = 0; i < n_vars; ++i)
+      if (!std::isfinite(cost[i])) return set_error(BDDMP_NONFINITE, "cost " + std::to_string(i) + " is not finite");
     auto *h = new bddmp_problem();
     h->p.n = n_vars;
     h->p.cost.assign(cost, cost + n_vars);
@@ -90,6 +93,19 @@ int32_t bddmp_problem_add_rows(bddmp_problem *h, int32_t n_rows, const int64_t *
       if (col[base + q] < 0 || col[base + q] >= p.n) return set_error(BDDMP_INVALID_ARG, "column out of range");
     for (int32_t r = 0; r < n_rows; ++r)
       if (sense[r] < 0 || sense[r] > 2) return set_error(BDDMP_INVALID_ARG, "sense must be 0, 1 or 2");
+    // the builders add coefficients to partial sums and compare them with the right-hand side in
+    // int64: keep every such sum below 2^62
+    constexpr int64_t kMag = int64_t(1) << 62;
+    for (int32_t r = 0; r < n_rows; ++r) {
+      if (rhs[r] <= -kMag || rhs[r] >= kMag) return set_error(BDDMP_INVALID_ARG, "row " + std::to_string(r) + ": |rhs| >= 2^62");
+      int64_t mag = rhs[r] < 0 ? -rhs[r] : rhs[r];
+      for (int64_t q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+        const int64_t a = coef[q];
+        if (a <= -kMag || a >= kMag || (a < 0 ? -a : a) >= kMag - mag)
+          return set_error(BDDMP_INVALID_ARG, "row " + std::to_string(r) + ": sum of |coefficients| + |rhs| >= 2^62");
+        mag += a < 0 ? -a : a;
+      }
+    }
     const int64_t off = p.row_ptr.back();
     for (int32_t r = 0; r < n_rows; ++r) p.row_ptr.push_back(off + row_ptr[r + 1] - base);
     p.col.insert(p.col.end(), col + base, col + base + nnz);
@@ -97,6 +113,35 @@ int32_t bddmp_problem_add_rows(bddmp_problem *h, int32_t n_rows, const int64_t *
     p.sense.insert(p.sense.end(), sense, sense + n_rows);
     p.rhs.insert(p.rhs.end(), rhs, rhs + n_rows);
     return int32_t(BDDMP_OK);
+  });
+}
+
+int32_t bddmp_problem_add_rows_real(bddmp_problem *h, int32_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                                    const double *coef, const int8_t *sense, const double *rhs) {
+  return guarded([&] {
+    if (!h || n_rows < 0) return set_error(BDDMP_INVALID_ARG, "null problem or negative row count");
+    if (n_rows == 0) return int32_t(BDDMP_OK);
+    if (!row_ptr || !sense || !rhs) return set_error(BDDMP_INVALID_ARG, "null row array");
+    for (int32_t r = 0; r < n_rows; ++r)
+      if (row_ptr[r + 1] < row_ptr[r]) return set_error(BDDMP_INVALID_ARG, "row_ptr not non-decreasing");
+    const int64_t base = row_ptr[0], nnz = row_ptr[n_rows] - base;
+    if (nnz > 0 && !coef) return set_error(BDDMP_INVALID_ARG, "null coef");
+    constexpr double kExact = 9007199254740992.0;  // 2^53: every integer below it is a double
+    auto integral = [&](double v) { return std::isfinite(v) && std::fabs(v) < kExact && std::trunc(v) == v; };
+    std::vector<int64_t> ci(static_cast<size_t>(nnz)), bi(static_cast<size_t>(n_rows));
+    for (int64_t q = 0; q < nnz; ++q) {
+      if (!integral(coef[base + q]))
+        return set_error(BDDMP_NOT_INTEGER, "coefficient " + std::to_string(base + q) + " is not an integer below 2^53");
+      ci[size_t(q)] = int64_t(coef[base + q]);
+    }
+    for (int32_t r = 0; r < n_rows; ++r) {
+      if (!integral(rhs[r]))
+        return set_error(BDDMP_NOT_INTEGER, "right-hand side " + std::to_string(r) + " is not an integer below 2^53");
+      bi[size_t(r)] = int64_t(rhs[r]);
+    }
+    std::vector<int64_t> rp(size_t(n_rows) + 1);
+    for (int32_t r = 0; r <= n_rows; ++r) rp[size_t(r)] = row_ptr[r] - base;
+    return bddmp_problem_add_rows(h, n_rows, rp.data(), col ? col + base : nullptr, ci.data(), sense, bi.data());
   });
 }
 

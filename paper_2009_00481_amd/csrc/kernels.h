@@ -50,6 +50,7 @@ struct Dev {
   double *inst_lb;          // [n_inst] per-instance bounds
   double *lbc;              // [2] bound constants of the variables in no row: min-plus, smoothed
   long long *hist_n;        // bounds recorded so far (device counter; slot = count % hist_cap)
+  unsigned *flag;           // set to 1 by the finiteness checks of device inputs
   int32_t hist_cap;
   uint32_t gsel;            // per tile width class, 4 bits: log2 of the lanes per general layer
                             // (0..6), or kFlat for the node-parallel tile path
@@ -78,6 +79,11 @@ hipError_t launch_init_lambda(const Dev &D, int I, hipStream_t s);
 hipError_t launch_root_zero(const Dev &D, int m, hipStream_t s);
 hipError_t launch_lambda_out(const Dev &D, float *out, int I, hipStream_t s);
 hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s);
+// D.flag = 0 (clear), then D.flag = 1 if any of the n values is NaN or infinite (the check may run
+// several times between one clear and the read of the flag).
+hipError_t launch_flag_clear(const Dev &D, hipStream_t s);
+hipError_t launch_nonfinite(const Dev &D, const float *p, int64_t n, hipStream_t s);
+hipError_t launch_nonfinite(const Dev &D, const double *p, int64_t n, hipStream_t s);
 // Bound of the backward sweep just run into the history ring at the device counter's slot, then
 // the counter advances (no host-side argument changes between iterations, so graphs can replay it).
 // which: 0 adds the min-plus constant D.lbc[0], 1 the smoothed one D.lbc[1].

@@ -14,6 +14,7 @@
 // record and loop over their nodes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -687,6 +688,18 @@ __global__ void lambda_in_kernel(const Dev D, const float *in, int I) {
   if (L < I) D.lam[L] = in[D.canon_of[L]];
 }
 
+__global__ void flag_clear_kernel(const Dev D) {
+  if (threadIdx.x == 0) *D.flag = 0u;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void nonfinite_kernel(const Dev D, const T *p, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  bool bad = false;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) bad |= !isfinite(p[i]);
+  if (bad) atomicOr(D.flag, 1u);
+}
+
 // LB = sum_j E^j (problem (D)) from the per-tile partials of the backward sweep: kLbStage blocks
 // each sum one fixed contiguous chunk, then one block sums the chunk totals; fixed order throughout
 __global__ __launch_bounds__(256) void lb_stage_kernel(const Dev D, int nparts) {
@@ -952,6 +965,25 @@ hipError_t launch_lambda_in(const Dev &D, const float *in, int I, hipStream_t s)
   if (I <= 0) return hipSuccess;
   hipLaunchKernelGGL(lambda_in_kernel, dim3(blocks_for(I, 256)), dim3(256), 0, s, D, in, I);
   return hipGetLastError();
+}
+
+hipError_t launch_flag_clear(const Dev &D, hipStream_t s) {
+  hipLaunchKernelGGL(flag_clear_kernel, dim3(1), dim3(64), 0, s, D);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t nonfinite_dispatch(const Dev &D, const T *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = int(std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(nonfinite_kernel<T>, dim3(blocks), dim3(256), 0, s, D, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_nonfinite(const Dev &D, const float *p, int64_t n, hipStream_t s) {
+  return nonfinite_dispatch(D, p, n, s);
+}
+hipError_t launch_nonfinite(const Dev &D, const double *p, int64_t n, hipStream_t s) {
+  return nonfinite_dispatch(D, p, n, s);
 }
 
 hipError_t launch_lb(const Dev &D, int nparts, int which, hipStream_t s) {

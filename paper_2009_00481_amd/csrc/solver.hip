@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -56,6 +57,21 @@ int32_t hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 int32_t launched(hipError_t e, const char *what) { return e == hipSuccess ? BDDMP_OK : hip_fail(e, what); }
+
+// NONFINITE unless every value of the device arrays (float or double, n each) is finite; checked on
+// the device, then the stream is synchronised to read the result.
+template <class T>
+int32_t check_finite(Solver &S, std::initializer_list<const T *> arrays, int64_t n, const char *what) {
+  if (n <= 0) return BDDMP_OK;
+  if (int32_t rc = launched(launch_flag_clear(S.D, S.stream), "flag_clear")) return rc;
+  for (const T *p : arrays)
+    if (int32_t rc = launched(launch_nonfinite(S.D, p, n, S.stream), "nonfinite check")) return rc;
+  unsigned bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, S.D.flag, sizeof bad, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
+  if (bad) return set_error(BDDMP_NONFINITE, std::string(what) + " holds NaN or infinite values");
+  return BDDMP_OK;
+}
 
 // Events around the pieces of an iteration for the timing entry point: the forward pass, the
 // backward pass and the bound, each bracketed as a whole (cls 0, 1, 2), so that the events add no
@@ -264,6 +280,7 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.out0 = D.out1 = nullptr;
   D.n_bwd_tiles = int32_t(P.bwd_tiles.size() / 2);
   D.hist_n = reinterpret_cast<long long *>(b + A.scal + 64);
+  D.flag = reinterpret_cast<unsigned *>(b + A.scal + 128);
   D.lbc = reinterpret_cast<double *>(b + A.scal + 80);
   D.hist_cap = P.hist_cap;
   D.inst_row = reinterpret_cast<const int32_t *>(b + A.inst_row);
@@ -426,7 +443,7 @@ int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_
   if (lb) *lb = h;
   if (residual) *residual = sc[0];
   if (any_lambda_bound) *any_lambda_bound = h + sc[1];
-  if (std::isnan(h)) return set_error(BDDMP_NONFINITE, "lower bound is NaN");
+  if (!std::isfinite(h)) return set_error(BDDMP_NONFINITE, std::isnan(h) ? "lower bound is NaN" : "lower bound is infinite");
   return BDDMP_OK;
 }
 
@@ -474,6 +491,7 @@ int32_t solver_get_lambda(Solver &S, float *lam) {
 
 int32_t solver_set_lambda(Solver &S, const float *lam) {
   const Plan &P = *S.plan;
+  if (int32_t rc = check_finite<float>(S, {lam}, P.I, "the multipliers")) return rc;
   if (int32_t rc = launched(launch_lambda_in(S.D, lam, int(P.I), S.stream), "lambda_in")) return rc;
   return initial_sweep(S);
 }
@@ -482,6 +500,8 @@ int32_t solver_copy_duals(Solver &S, bool out, float *mu_bar, float *mu, float *
   const Plan &P = *S.plan;
   if (!out && (!mu_bar || !mu || !dfw || !dbw) && P.n_copy)
     return set_error(BDDMP_INVALID_ARG, "setting the copy state needs all four arrays");
+  if (!out)
+    if (int32_t rc = check_finite<float>(S, {mu_bar, mu, dfw, dbw}, P.n_copy, "the copy-arc state")) return rc;
   if (int32_t rc = launched(launch_copy_io(S.D, int(P.n_cuts), out, mu_bar, mu, dfw, dbw, S.stream), "copy state"))
     return rc;
   return out ? BDDMP_OK : initial_sweep(S);
@@ -761,6 +781,7 @@ int32_t solver_smooth_grad(Solver &S, float alpha, int32_t T, void *ws, size_t b
 int32_t solver_set_costs(Solver &S, const double *cost_dev) {
   const Plan &P = *S.plan;
   if (!cost_dev && P.n > 0) return set_error(BDDMP_INVALID_ARG, "null costs");
+  if (int32_t rc = check_finite<double>(S, {cost_dev}, P.n, "the costs")) return rc;
   if (int32_t rc = launched(launch_cost_in(S.D, cost_dev, P.n, S.stream), "cost_in")) return rc;
   S.costs_replaced = true;
   return BDDMP_OK;

@@ -352,6 +352,21 @@ int32_t bddmp_solver_smooth_grad(bddmp_solver *s, float alpha, int32_t n_iters, 
                                  double dlb, float *grad_dev);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): bddmp_solver_smooth_run followed by
+ * bddmp_solver_smooth_grad with the same alpha and n_iters, without a workspace argument. The
+ * workspace is a static array in the library's device code, 64 MiB (67108864 bytes) on each GPU
+ * the library runs on, allocated when the library's code is loaded on that GPU and held until the
+ * process ends; this call itself allocates nothing. Results, bound history and the solver's final
+ * state are those of the two calls with a caller workspace. INVALID_ARG, before any device work, if
+ * bddmp_smooth_workspace_bytes(plan, n_iters) exceeds 64 MiB. Every call on one GPU uses that GPU's
+ * one array: calls that overlap in time on one GPU (from several threads, or on several streams
+ * without ordering between them) race and give undefined results. Asynchronous. grad_dev: device
+ * float [n_vars].
+ */
+int32_t bddmp_solver_smooth_grad_noalloc(bddmp_solver *s, float alpha, int32_t n_iters, double dlb, float *grad_dev);
+
+/*
  * Replaces the costs c (device double [n_vars]) used by bddmp_solver_reset and the smoothed run
  * (lambda = c / |J_i| and the terms of variables in no row). The plan keeps its own costs: after
  * this call bddmp_solver_instance_bounds returns BAD_STATE. The values are checked on the device

@@ -92,6 +92,7 @@ SIGNATURES = {
     "bddmp_smooth_workspace_bytes": (_I32, [_P, _I32, C.POINTER(C.c_size_t)]),
     "bddmp_solver_smooth_run": (_I32, [_P, C.c_float, _I32, _P, C.c_size_t]),
     "bddmp_solver_smooth_grad": (_I32, [_P, C.c_float, _I32, _P, C.c_size_t, _D, _P]),
+    "bddmp_solver_smooth_grad_noalloc": (_I32, [_P, C.c_float, _I32, _D, _P]),
     "bddmp_solver_set_costs": (_I32, [_P, _P]),
     "bddmp_solver_set_graphs": (_I32, [_P, _I32]),
     "bddmp_solver_set_groups": (_I32, [_P, _P]),
@@ -347,6 +348,10 @@ def bddmp_solver_smooth_run(h, alpha: float, n_iters: int, ws, ws_bytes: int):
 def bddmp_solver_smooth_grad(h, alpha: float, n_iters: int, ws, ws_bytes: int, dlb: float, grad):
     _check(lib().bddmp_solver_smooth_grad(h, float(alpha), int(n_iters), _dptr(ws), C.c_size_t(int(ws_bytes)),
                                           float(dlb), _dptr(grad)))
+
+
+def bddmp_solver_smooth_grad_noalloc(h, alpha: float, n_iters: int, dlb: float, grad):
+    _check(lib().bddmp_solver_smooth_grad_noalloc(h, float(alpha), int(n_iters), float(dlb), _dptr(grad)))
 
 
 def bddmp_solver_set_costs(h, cost):

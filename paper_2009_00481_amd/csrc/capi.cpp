@@ -416,6 +416,11 @@ int32_t bddmp_solver_smooth_grad(bddmp_solver *h, float alpha, int32_t n_iters, 
   return guarded([&] { return bddmp::solver_smooth_grad(*h->s, alpha, n_iters, ws, ws_bytes, dlb, grad_dev); });
 }
 
+int32_t bddmp_solver_smooth_grad_noalloc(bddmp_solver *h, float alpha, int32_t n_iters, double dlb, float *grad_dev) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_smooth_grad_noalloc(*h->s, alpha, n_iters, dlb, grad_dev); });
+}
+
 int32_t bddmp_solver_set_costs(bddmp_solver *h, const double *cost_dev) {
   SOLVER_OR_FAIL(h);
   return bddmp::solver_set_costs(*h->s, cost_dev);

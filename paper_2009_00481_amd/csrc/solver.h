@@ -33,6 +33,9 @@ int32_t solver_smooth_workspace(const Plan &P, int32_t T, size_t *bytes);
 int32_t solver_smooth_run(Solver &S, float alpha, int32_t T, void *ws, size_t bytes);
 int32_t solver_smooth_grad(Solver &S, float alpha, int32_t T, void *ws, size_t bytes, double dlb, float *grad);
 int32_t solver_set_costs(Solver &S, const double *cost_dev);
+// bytes of the static scratch that solver_smooth_grad_noalloc uses as its workspace
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+int32_t solver_smooth_grad_noalloc(Solver &S, float alpha, int32_t T, double dlb, float *grad);
 void solver_destroy(Solver *S);
 
 }  // namespace bddmp

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -776,6 +777,63 @@ int32_t solver_smooth_grad(Solver &S, float alpha, int32_t T, void *ws, size_t b
   if (int32_t rc = launched(launch_smooth_grad(S.D, A, P.n, float(dlb), grad, S.stream), "smooth_grad")) return rc;
   HIP_TRY(copy_f(S.D.lam, w.ckpt + I1 * size_t(T), P.I, S.stream), "hipMemcpyAsync");
   return smooth_pass(S, kBwd, kNoUpdate, false, A);
+}
+
+// ---------------------------------------------------------------------------------------------
+// smoothed gradient without a caller workspace (for callers that cannot allocate device memory)
+// ---------------------------------------------------------------------------------------------
+
+namespace {
+
+// The workspace of solver_smooth_grad_noalloc: a fixed array in the code object, one copy per GPU,
+// allocated when the library's code is loaded on that GPU and held until the process ends. Calls on
+// one GPU share it. In host code `scratch` names a host-side stand-in, never the device memory:
+// only the address hipGetSymbolAddress returns for a device is passed on.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device ordinal: the array's address on that device
+
+// The array's address on the GPU that holds the solver's arena, looked up once per device with that
+// device current.
+int32_t scratch_of(const Solver &S, void *&out) {
+  hipPointerAttribute_t attr{};
+  HIP_TRY(hipPointerGetAttributes(&attr, S.arena), "hipPointerGetAttributes");
+  const int dev = attr.device;
+  if (dev < 0) return set_error(BDDMP_DEVICE, "the solver's arena is not device memory");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[size_t(dev)]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) HIP_TRY(hipSetDevice(dev), "hipSetDevice");
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIP_TRY(hipSetDevice(cur), "hipSetDevice");
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static scratch)");
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256) return set_error(BDDMP_DEVICE, "static scratch misplaced");
+    g_scratch_ptr[size_t(dev)] = p;
+  }
+  out = g_scratch_ptr[size_t(dev)];
+  return BDDMP_OK;
+}
+
+}  // namespace
+
+int32_t solver_smooth_grad_noalloc(Solver &S, float alpha, int32_t T, double dlb, float *grad) {
+  const Plan &P = *S.plan;
+  if (T < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
+  size_t need = 0;
+  if (int32_t rc = solver_smooth_workspace(P, T, &need)) return rc;
+  if (need > kNoAllocScratchBytes)
+    return set_error(BDDMP_INVALID_ARG, "workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                                            std::to_string(kNoAllocScratchBytes) + " bytes");
+  void *ws = nullptr;
+  if (int32_t rc = scratch_of(S, ws)) return rc;
+  // the run writes every checkpoint before the gradient reads it, and the gradient clears its
+  // adjoint arrays itself: nothing left by an earlier call is read
+  if (int32_t rc = solver_smooth_run(S, alpha, T, ws, kNoAllocScratchBytes)) return rc;
+  return solver_smooth_grad(S, alpha, T, ws, kNoAllocScratchBytes, dlb, grad);
 }
 
 int32_t solver_set_costs(Solver &S, const double *cost_dev) {

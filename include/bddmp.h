@@ -95,6 +95,11 @@ typedef struct {
   int32_t fused_wrap;           /* 1 if, inside a run of iterations, the last backward wave
                                    and the next iteration's first forward wave run as one
                                    launch (their levels are the rows' roots)                */
+  int32_t dataflow;             /* 1 if the plan supports the dataflow launch of a pass
+                                   (bddmp_solver_set_launch; no variable in > 256 rows)     */
+  int32_t max_tile_deps;        /* most tiles one tile waits for in the dataflow launch    */
+  int32_t n_groups;             /* groups of instances, one ticket queue each (dataflow)    */
+  int64_t tile_deps_fwd, tile_deps_bwd; /* tile-to-tile dependencies per pass              */
 } bddmp_stats;
 
 typedef struct {
@@ -221,6 +226,18 @@ int32_t bddmp_plan_export_order(const bddmp_plan *plan, int32_t *perm_out);
  */
 int32_t bddmp_plan_export_structure(const bddmp_plan *plan, int32_t *level_width, int32_t *level_var,
                                     int32_t *lo, int32_t *hi);
+
+/*
+ * Tile schedule of one pass of the dataflow launch (bddmp_solver_set_launch), for inspection and
+ * host-side checks: pass 0 forward, 1 backward; dep_ptr host [tiles + 1] (tiles: fwd_tiles or
+ * bwd_tiles of bddmp_stats), dep_list host [tile_deps_fwd or tile_deps_bwd]: the tiles tile t waits
+ * for are dep_list[dep_ptr[t] .. dep_ptr[t+1]), ascending, each smaller than t; tile_group host
+ * [tiles]: the group of instances (ticket queue) of each tile, 0 .. n_groups - 1, the same for a
+ * tile and every tile it waits for. Any pointer may be NULL. INVALID_ARG for a plan without
+ * dataflow support.
+ */
+int32_t bddmp_plan_export_tile_deps(const bddmp_plan *plan, int32_t pass, int32_t *dep_ptr, int32_t *dep_list,
+                                    int32_t *tile_group);
 
 /* Forward and backward wave of every variable (1-based, 0 for variables in no row); host [n_vars]. */
 int32_t bddmp_plan_export_waves(const bddmp_plan *plan, int32_t *wave_fwd, int32_t *wave_bwd);
@@ -385,6 +402,25 @@ int32_t bddmp_solver_set_costs(bddmp_solver *s, const double *cost_dev);
  * iterations. enable = 0: every wave is launched from the host. Both give bitwise the same results.
  */
 int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
+
+/*
+ * Launch form of the update passes of bddmp_solver_iterate (and of the timing and autotuning calls).
+ * mode 0 (default): one launch per dependency wave, each wave a barrier for the next (with the
+ * turnaround and wrap-around fusions of bddmp_stats). mode 1 (dataflow; plans with
+ * bddmp_stats.dataflow = 1): one launch per pass whose workgroups stay resident and take tiles
+ * (256 layers of whole variables) in the pass's wave order through a device ticket, chunk tiles per
+ * ticket (0: 1). A tile starts as soon as the tiles holding the previous levels (forward pass) or
+ * the next levels (backward pass) of its rows are done, instead of after the whole previous wave,
+ * so independent rows and instances proceed at their own pace; every value computed is the same
+ * as with wave launches (the same operations in the same order per layer). Each wait for another
+ * tile is bounded; a wait that exceeds its bound (about a second; not expected while the GPU runs
+ * only this work) makes the next lower_bound / lb_history return DEVICE until bddmp_solver_reset.
+ * INVALID_ARG for mode 1 on a plan without dataflow support. get: either pointer may be NULL.
+ * For tests of that failure path, the environment variable BDDMP_PASS_SPIN_LIMIT (read by this
+ * call) replaces the bound: the polls of one wait before it gives up.
+ */
+int32_t bddmp_solver_set_launch(bddmp_solver *s, int32_t mode, int32_t chunk);
+int32_t bddmp_solver_get_launch(const bddmp_solver *s, int32_t *mode, int32_t *chunk);
 
 /*
  * Path of the general layers (a level or its next level with more than 2 nodes). Tiles are classed

@@ -42,7 +42,9 @@ class Stats(C.Structure):
                 ("n_shapes", C.c_int32), ("max_rows_per_var", C.c_int32), ("bwd_contiguous", C.c_int32),
                 ("fwd_tiles", C.c_int64), ("bwd_tiles", C.c_int64), ("n_instances", C.c_int32),
                 ("n_intervals", C.c_int32), ("n_cuts", C.c_int64), ("n_copy_pairs", C.c_int64),
-                ("fused_turn", C.c_int32), ("fused_wrap", C.c_int32)]
+                ("fused_turn", C.c_int32), ("fused_wrap", C.c_int32), ("dataflow", C.c_int32),
+                ("max_tile_deps", C.c_int32), ("n_groups", C.c_int32), ("tile_deps_fwd", C.c_int64),
+                ("tile_deps_bwd", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +78,7 @@ SIGNATURES = {
     "bddmp_plan_export_order": (_I32, [_P, _P]),
     "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_plan_export_waves": (_I32, [_P, _P, _P]),
+    "bddmp_plan_export_tile_deps": (_I32, [_P, _I32, _P, _P, _P]),
     "bddmp_solver_bind": (_I32, [_P, _P, C.c_size_t, _P, C.POINTER(_P)]),
     "bddmp_solver_reset": (_I32, [_P]),
     "bddmp_solver_iterate": (_I32, [_P, _I32]),
@@ -95,6 +98,8 @@ SIGNATURES = {
     "bddmp_solver_smooth_grad_noalloc": (_I32, [_P, C.c_float, _I32, _D, _P]),
     "bddmp_solver_set_costs": (_I32, [_P, _P]),
     "bddmp_solver_set_graphs": (_I32, [_P, _I32]),
+    "bddmp_solver_set_launch": (_I32, [_P, _I32, _I32]),
+    "bddmp_solver_get_launch": (_I32, [_P, C.POINTER(_I32), C.POINTER(_I32)]),
     "bddmp_solver_set_groups": (_I32, [_P, _P]),
     "bddmp_solver_get_groups": (_I32, [_P, _P]),
     "bddmp_solver_autotune": (_I32, [_P, _I32, _P]),
@@ -267,6 +272,14 @@ def bddmp_plan_export_waves(plan, n: int):
     return f[:n], b[:n]
 
 
+def bddmp_plan_export_tile_deps(plan, pass_: int, n_tiles: int, n_deps: int):
+    ptr = np.zeros(n_tiles + 1, np.int32)
+    lst = np.zeros(max(n_deps, 1), np.int32)
+    grp = np.zeros(max(n_tiles, 1), np.int32)
+    _check(lib().bddmp_plan_export_tile_deps(plan, int(pass_), _ptr(ptr), _ptr(lst), _ptr(grp)))
+    return ptr, lst[:n_deps], grp[:n_tiles]
+
+
 def bddmp_solver_bind(plan, arena, nbytes: int, stream):
     h = C.c_void_p()
     _check(lib().bddmp_solver_bind(plan, _dptr(arena), C.c_size_t(int(nbytes)), C.c_void_p(stream), C.byref(h)))
@@ -360,6 +373,16 @@ def bddmp_solver_set_costs(h, cost):
 
 def bddmp_solver_set_graphs(h, enable: bool):
     _check(lib().bddmp_solver_set_graphs(h, int(bool(enable))))
+
+
+def bddmp_solver_set_launch(h, mode: int, chunk: int = 0):
+    _check(lib().bddmp_solver_set_launch(h, int(mode), int(chunk)))
+
+
+def bddmp_solver_get_launch(h):
+    m, c = C.c_int32(), C.c_int32()
+    _check(lib().bddmp_solver_get_launch(h, C.byref(m), C.byref(c)))
+    return m.value, c.value
 
 
 def bddmp_solver_set_groups(h, lanes):
@@ -466,6 +489,12 @@ class Plan:
     def waves(self):
         return bddmp_plan_export_waves(self.h, self.n)
 
+    def tile_deps(self, pass_: int):
+        """(dep_ptr, dep_list, tile_group) of the dataflow launch's tiles in pass 0 (forward) or 1 (backward)."""
+        st = self.stats
+        n = int(st.fwd_tiles if pass_ == 0 else st.bwd_tiles)
+        return bddmp_plan_export_tile_deps(self.h, pass_, n, int(st.tile_deps_fwd if pass_ == 0 else st.tile_deps_bwd))
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             bddmp_plan_destroy(self.h)
@@ -547,6 +576,12 @@ class Solver:
 
     def set_graphs(self, enable: bool):
         bddmp_solver_set_graphs(self.h, enable)
+
+    def set_launch(self, mode: int, chunk: int = 0):
+        bddmp_solver_set_launch(self.h, mode, chunk)
+
+    def launch(self):
+        return bddmp_solver_get_launch(self.h)
 
     def set_groups(self, lanes):
         bddmp_solver_set_groups(self.h, lanes)

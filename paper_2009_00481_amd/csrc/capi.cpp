@@ -1,4 +1,5 @@
 // C-ABI of bddmp: argument checks, handle ownership, status codes and the last-error message.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -276,6 +277,12 @@ int32_t bddmp_plan_stats(const bddmp_plan *h, bddmp_stats *out) {
   out->n_copy_pairs = P.n_copy;
   out->fused_turn = P.fuse_turn ? 1 : 0;
   out->fused_wrap = P.fuse_wrap ? 1 : 0;
+  out->dataflow = P.pers_ok ? 1 : 0;
+  out->n_groups = P.n_groups;
+  out->tile_deps_fwd = int64_t(P.fdep_list.size());
+  out->tile_deps_bwd = int64_t(P.bdep_list.size());
+  for (const auto *ptr : {&P.fdep_ptr, &P.bdep_ptr})
+    for (size_t t = 0; t + 1 < ptr->size(); ++t) out->max_tile_deps = std::max(out->max_tile_deps, (*ptr)[t + 1] - (*ptr)[t]);
   return BDDMP_OK;
 }
 
@@ -301,6 +308,25 @@ int32_t bddmp_plan_export_structure(const bddmp_plan *h, int32_t *level_width, i
       if (lo) lo[qn] = sh.lo[u];
       if (hi) hi[qn] = sh.hi[u];
     }
+  }
+  return BDDMP_OK;
+}
+
+int32_t bddmp_plan_export_tile_deps(const bddmp_plan *h, int32_t pass, int32_t *dep_ptr, int32_t *dep_list,
+                                    int32_t *tile_group) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  if (pass != 0 && pass != 1) return set_error(BDDMP_INVALID_ARG, "pass must be 0 (forward) or 1 (backward)");
+  const bddmp::Plan &P = h->plan;
+  if (!P.pers_ok) return set_error(BDDMP_INVALID_ARG, "the plan has no dataflow launch");
+  const auto &ptr = pass ? P.bdep_ptr : P.fdep_ptr;
+  const auto &lst = pass ? P.bdep_list : P.fdep_list;
+  if (dep_ptr) std::memcpy(dep_ptr, ptr.data(), sizeof(int32_t) * ptr.size());
+  if (dep_list && !lst.empty()) std::memcpy(dep_list, lst.data(), sizeof(int32_t) * lst.size());
+  if (tile_group) {
+    const auto &qptr = pass ? P.bqptr : P.fqptr;
+    const auto &qtile = pass ? P.bqtile : P.fqtile;
+    for (size_t g = 0; g + 1 < qptr.size(); ++g)
+      for (int32_t k = qptr[g]; k < qptr[g + 1]; ++k) tile_group[qtile[size_t(k)]] = int32_t(g);
   }
   return BDDMP_OK;
 }
@@ -429,6 +455,16 @@ int32_t bddmp_solver_set_costs(bddmp_solver *h, const double *cost_dev) {
 int32_t bddmp_solver_set_graphs(bddmp_solver *h, int32_t enable) {
   SOLVER_OR_FAIL(h);
   return bddmp::solver_set_graphs(*h->s, enable);
+}
+
+int32_t bddmp_solver_set_launch(bddmp_solver *h, int32_t mode, int32_t chunk) {
+  SOLVER_OR_FAIL(h);
+  return guarded([&] { return bddmp::solver_set_launch(*h->s, mode, chunk); });
+}
+
+int32_t bddmp_solver_get_launch(const bddmp_solver *h, int32_t *mode, int32_t *chunk) {
+  SOLVER_OR_FAIL(h);
+  return bddmp::solver_get_launch(*h->s, mode, chunk);
 }
 
 int32_t bddmp_solver_set_groups(bddmp_solver *h, const int32_t *lanes) {

@@ -17,9 +17,47 @@ __device__ __forceinline__ float c2val(uint32_t code, float2 b) {
   return (code & 2u) ? term : node;
 }
 
+// Message accesses. In the dataflow launch (pass_kernel) a tile reads messages that other tiles of
+// the same launch wrote, possibly on another XCD with its own L2. With COH those loads and stores
+// are relaxed atomics at agent scope, which the hardware keeps coherent across the device without
+// write-back or invalidation of the caches; the wave launches use plain accesses (the kernel
+// boundary between waves orders them).
+template <bool COH>
+__device__ __forceinline__ float msg_ld(const float *p) {
+  if constexpr (COH) return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+// the float pair at p (8-byte aligned)
+template <bool COH>
+__device__ __forceinline__ float2 msg_ld2(const float *p) {
+  if constexpr (COH) {
+    const unsigned long long v = __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<float *>(p)),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float(unsigned(v)), __uint_as_float(unsigned(v >> 32)));
+  } else {
+    return *reinterpret_cast<const float2 *>(p);
+  }
+}
+template <bool COH>
+__device__ __forceinline__ void msg_st(float *p, float v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void msg_st2(float *p, float2 v) {
+  if constexpr (COH) {
+    const unsigned long long w =
+        (static_cast<unsigned long long>(__float_as_uint(v.y)) << 32) | static_cast<unsigned long long>(__float_as_uint(v.x));
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *reinterpret_cast<float2 *>(p) = v;
+  }
+}
+
 // backward message behind a 16-bit child code of a general layer
+template <bool COH = false>
 __device__ __forceinline__ float c16val(const float *__restrict__ mb, int cs, uint32_t c) {
-  return c < kTop ? mb[cs + int(c)] : (c == kTop ? 0.0f : INFINITY);
+  return c < kTop ? msg_ld<COH>(mb + cs + int(c)) : (c == kTop ? 0.0f : INFINITY);
 }
 
 // General record of a layer: own slot, child slot, own width, child width, base of the child

@@ -18,6 +18,11 @@ constexpr int kBigMax = 4096;           // max rows of one variable (J_i) a wave
 constexpr int kLbBlocks = 1024;         // fixed partial count of the deterministic fp64 reductions
 constexpr int kCutsPerBlock = 4;        // wide cuts per workgroup of the copy-arc kernels (one wavefront each)
 
+// Control words of one pass's dataflow launch (uint32 offsets): generation of the last launch,
+// workgroups gone, error word, then kPassQueues ticket counters, each on a 128-byte line of its own.
+constexpr int kPassGen = 0, kPassGone = 1, kPassErr = 2, kPassQueue0 = 32, kPassQueues = 32, kPassQueueStride = 32;
+constexpr int kPassCtlWords = kPassQueue0 + kPassQueues * kPassQueueStride;
+
 // 2-bit child codes of a narrow layer (both its level and the next have at most 2 nodes)
 constexpr uint32_t kC2Bot = 2u, kC2Top = 3u;
 
@@ -84,6 +89,7 @@ struct Problem {
 // Byte offsets of the solver's arrays inside the device arena.
 struct ArenaLayout {
   size_t meta, child, parent, lam, mf, mbc, garcs, grec, gnb, rbeg, rin, rarc, canon_of, layer_of, layer_var, root_slot;
+  size_t fdep_list, bdep_list, ftrec, btrec, fqptr, fqtile, bqptr, bqtile, fflag, bflag, pctl;
   size_t fwd_tiles, bwd_tiles, bwd_list, fwd_big, bwd_big;
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
@@ -178,6 +184,25 @@ struct Plan {
   std::vector<int32_t> cut_row;       // [n_cuts] row of each cut record (host)
   std::vector<int32_t> exit_rec;      // [I] with a split: the cut record whose exit layer this is, or -1
   std::vector<uint16_t> cut_arc;
+  // Dataflow launch of a pass (one persistent launch; workgroups take tiles in pass order through a
+  // device ticket): per normal tile of each pass, the tiles that write the messages it reads (the
+  // tiles holding the parent layers of its layers in the forward pass, the child layers' tiles in
+  // the backward pass), deduplicated and ascending, as CSR (dep_ptr [tiles + 1], dep_list). All of
+  // them lie in earlier waves, so their indices are smaller than the tile's own. tinfo per tile: bit
+  // 0 every layer is narrow, bit 1 positions go through bwd_list, bits 2-3 wave priority (3 for tiles
+  // on the pass's longest dependency chains, lower with more slack). Plans with big tiles have none
+  // (pers_ok false).
+  bool pers_ok = false;
+  std::vector<int32_t> fdep_ptr, fdep_list, bdep_ptr, bdep_list;
+  std::vector<uint32_t> ftinfo, btinfo;
+  // the same per tile as the kernel reads it, 8 words: start word, end word, tinfo | dependency
+  // count << 8, offset of its dependencies in dep_list, then the first four dependencies (-1 pads)
+  std::vector<int32_t> ftrec, btrec;
+  // groups of instances (one ticket queue each in the dataflow launch): group of each variable, and
+  // per pass each group's tiles in pass order (CSR over groups)
+  int32_t n_groups = 1;
+  std::vector<int32_t> var_group;
+  std::vector<int32_t> fqptr, fqtile, bqptr, bqtile;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes
   uint32_t gsel = kDefaultGsel;

@@ -71,6 +71,23 @@ struct Dev {
 // kWrap (dir kFwd, narrow-only, no list): bwd_tile0 is the first backward tile of the same levels.
 hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, int tile0, const Dev &D,
                        hipStream_t s, int bwd_tile0 = 0);
+// Dataflow launch of one pass (update mode; plans without big tiles): the pass's tiles in ticket
+// order, each after the tiles it depends on (see pass_kernel in kernels.hip).
+struct PassArgs {
+  const int4 *trec;                   // per tile, 2 int4: start, end, info | deps << 8, list offset; deps
+  const int32_t *dep_list;            // dependencies of tiles with more than four
+  const int32_t *qptr, *qtile;        // each group's tiles in pass order (CSR over n_queues groups)
+  uint32_t *flags;                    // per tile: generation of the launch that finished it
+  uint32_t *ctl;                      // kPassCtlWords control words (internal.h)
+  int32_t n_tiles;
+  int32_t n_queues;                   // groups of instances, one ticket counter each (<= kPassQueues)
+  int32_t chunk;                      // consecutive tiles of a queue per ticket (>= 1)
+  uint32_t spin_limit;                // polls of one flag before the wait gives up (error word)
+};
+hipError_t launch_pass(int dir, bool narrow_plan, int grid, const Dev &D, const PassArgs &A, hipStream_t s);
+// Resident workgroups per CU of the pass kernel (the launch's grid is this times the CU count).
+hipError_t pass_blocks_per_cu(int dir, bool narrow_plan, int *blocks);
+
 // Big tiles (one variable with more than kTile rows each) of one wave.
 hipError_t launch_wave_big(int dir, int mode, bool list, int nb, int big0, const Dev &D, hipStream_t s);
 

@@ -42,8 +42,9 @@ __device__ __forceinline__ float updated(float lam0, float d, float share, int n
 // NARROW_ONLY instantiations serve waves without wide levels: no per-lane branch, so the compiler
 // issues all loads at once instead of sinking the message loads behind the meta word.
 // LOOP: a general layer is handled by its own lane, looping over its nodes (big tiles); otherwise
-// general layers are left to the lane groups of the wave kernel.
-template <int DIR, bool NARROW_ONLY, bool LOOP>
+// general layers are left to the lane groups of the wave kernel. COH: messages of this pass are
+// read and written coherently (dataflow launch; see msg_ld).
+template <int DIR, bool NARROW_ONLY, bool LOOP, bool COH = false>
 struct Layer {
   int L;
   int tgt;
@@ -61,8 +62,8 @@ struct Layer {
     meta = D.meta[L];
     lam0 = D.lam[L];
     tgt = DIR == kFwd ? D.child[L] : D.parent[L];
-    f = reinterpret_cast<const float2 *>(D.mf)[L];
-    b = reinterpret_cast<const float2 *>(D.mbc)[L];
+    f = msg_ld2<COH && DIR == kFwd>(D.mf + 2 * L);
+    b = msg_ld2<COH && DIR == kBwd>(D.mbc + 2 * L);
     // keep the five independent loads ahead of every use, so they are in flight together
     __builtin_amdgcn_sched_barrier(0);
     m0 = INFINITY;
@@ -101,7 +102,7 @@ struct Layer {
                              fminf(k2 == 0u ? a2 : INFINITY, k3 == 0u ? a3 : INFINITY));
       const float c1 = fminf(fminf(k0 == 1u ? a0 : INFINITY, k1 == 1u ? a1 : INFINITY),
                              fminf(k2 == 1u ? a2 : INFINITY, k3 == 1u ? a3 : INFINITY));
-      reinterpret_cast<float2 *>(D.mf)[tgt] = make_float2(c0, c1);
+      msg_st2<COH>(D.mf + 2 * tgt, make_float2(c0, c1));
     } else if (LOOP) {
       const GRec g = grec_of(D, L);
       const int cs = D.grec[tgt].x;  // the child layer's own slots
@@ -131,7 +132,7 @@ struct Layer {
     if (narrow()) {
       const float n0 = fminf(c2val(meta & 3u, b), c2val((meta >> 2) & 3u, b) + lam1);
       const float n1 = fminf(c2val((meta >> 4) & 3u, b), c2val((meta >> 6) & 3u, b) + lam1);
-      if (tgt >= 0) reinterpret_cast<float2 *>(D.mbc)[tgt] = make_float2(n0, n1);
+      if (tgt >= 0) msg_st2<COH>(D.mbc + 2 * tgt, make_float2(n0, n1));
       r = n0;
     } else if (LOOP) {
       const GRec g = grec_of(D, L);
@@ -210,15 +211,16 @@ __device__ __forceinline__ float pull_min(const Dev &D, int rb, int v, float lam
 
 // min-marginals: each lane minimises over its nodes, then a butterfly min over the group (min is
 // exact, so the result does not depend on how nodes are split among lanes)
+template <int DIR, bool COH>
 __device__ __forceinline__ float2 group_mm(const Dev &D, const GenTile &T, int k, int gl, int G) {
   const int os = T.os[k], cs = T.cs[k], w = T.ww[k] & 0xFFFF;
   const float lam0 = T.lam[k];
   float m0 = INFINITY, m1 = INFINITY;
   for (int u = gl; u < w; u += G) {
     const uint32_t a = D.garcs[os + u];
-    const float fu = D.mf[os + u];
-    m0 = fminf(m0, fu + c16val(D.mbc, cs, a & 0xFFFFu));
-    m1 = fminf(m1, (fu + lam0) + c16val(D.mbc, cs, a >> 16));
+    const float fu = msg_ld<COH && DIR == kFwd>(D.mf + os + u);
+    m0 = fminf(m0, fu + c16val<COH && DIR == kBwd>(D.mbc, cs, a & 0xFFFFu));
+    m1 = fminf(m1, (fu + lam0) + c16val<COH && DIR == kBwd>(D.mbc, cs, a >> 16));
   }
   for (int o = G >> 1; o > 0; o >>= 1) {
     m0 = fminf(m0, __shfl_xor(m0, o, 64));
@@ -229,40 +231,29 @@ __device__ __forceinline__ float2 group_mm(const Dev &D, const GenTile &T, int k
 
 // forward step of the next level in pull form: each lane takes next-level nodes and minimises
 // over their in-arcs (Alg. "Forward BDD update step"), so no two lanes write one slot
+template <bool COH>
 __device__ __forceinline__ void group_push(const Dev &D, const GenTile &T, int k, int gl, int G) {
   const int osc = T.osc[k];
   if (osc < 0) return;
   const int os = T.os[k], wc = int(unsigned(T.ww[k]) >> 16), rb = T.rb[k];
   const float lam1 = T.lam[k];
-  for (int v = gl; v < wc; v += G) D.mf[osc + v] = pull_min(D, rb, v, lam1, [&](int u) { return D.mf[os + u]; });
+  for (int v = gl; v < wc; v += G)
+    msg_st<COH>(D.mf + osc + v, pull_min(D, rb, v, lam1, [&](int u) { return msg_ld<COH>(D.mf + os + u); }));
 }
 
 // backward step of this level, one node per lane; returns node 0's new message in lane 0
+template <bool COH>
 __device__ __forceinline__ float group_bstep(const Dev &D, const GenTile &T, int k, int gl, int G) {
   const int os = T.os[k], cs = T.cs[k], w = T.ww[k] & 0xFFFF, ps = T.pcs[k];
   const float lam1 = T.lam[k];
   float r = 0.0f;
   for (int u = gl; u < w; u += G) {
     const uint32_t a = D.garcs[os + u];
-    const float v = fminf(c16val(D.mbc, cs, a & 0xFFFFu), c16val(D.mbc, cs, a >> 16) + lam1);
-    if (ps >= 0) D.mbc[ps + u] = v;
+    const float v = fminf(c16val<COH>(D.mbc, cs, a & 0xFFFFu), c16val<COH>(D.mbc, cs, a >> 16) + lam1);
+    if (ps >= 0) msg_st<COH>(D.mbc + ps + u, v);
     if (u == 0) r = v;
   }
   return r;
-}
-
-// The layer holding node t of a tile's concatenated levels: the largest k < n with off[k] <= t
-// (off: exclusive prefix sums of the levels' widths, so non-decreasing with off[0] = 0; a level of
-// width 0 repeats its successor's offset and is passed over). A fixed-step binary search: every
-// lane takes the same 8 LDS reads, and searches for different nodes of a lane overlap.
-__device__ __forceinline__ int layer_of_node(const int *off, int n, int t) {
-  int k = 0;
-#pragma unroll
-  for (int step = kTile / 2; step > 0; step >>= 1) {
-    const int c = k + step;
-    if (c < n && off[c] <= t) k = c;
-  }
-  return k;
 }
 
 // Flat path: the tile's general nodes spread over all lanes (node t of the concatenated own
@@ -271,54 +262,125 @@ __device__ __forceinline__ int layer_of_node(const int *off, int n, int t) {
 constexpr int kFlatCap = 2048;             // own nodes and child nodes a tile may stage
 constexpr int kFlatR = kFlatCap / kTile;   // nodes per lane
 
+// The layers holding the lane's first N nodes s, s + kTile, ... (clamped to total - 1) of a tile's
+// concatenated levels: for node t, the largest k < n with off[k] <= t (off: exclusive prefix sums
+// of the levels' widths, so non-decreasing with off[0] = 0; a level of width 0 repeats its
+// successor's offset and is passed over). Fixed-step binary searches that advance together, so
+// their LDS reads are in flight at the same time: the lane waits for 8 read latencies, not 8 N.
+template <int N>
+__device__ __forceinline__ void layers_of_slots(const int *off, int n, int total, int s, int *k) {
+  int t[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    t[r] = min(s + r * kTile, total - 1);
+    k[r] = 0;
+  }
+#pragma unroll
+  for (int step = kTile / 2; step > 0; step >>= 1) {
+    int v[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = off[k[r] + step];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+      if (k[r] + step < n && v[r] <= t[r]) k[r] += step;
+  }
+}
+
+// the same for the first R slots, R = ceil(total / kTile) (uniform over the workgroup; 0 .. kFlatR)
+__device__ __forceinline__ void slot_layers(const int *off, int n, int total, int s, int *k) {
+  switch ((total + kTile - 1) / kTile) {
+    case 1: layers_of_slots<1>(off, n, total, s, k); break;
+    case 2: layers_of_slots<2>(off, n, total, s, k); break;
+    case 3: layers_of_slots<3>(off, n, total, s, k); break;
+    case 4: layers_of_slots<4>(off, n, total, s, k); break;
+    case 5: layers_of_slots<5>(off, n, total, s, k); break;
+    case 6: layers_of_slots<6>(off, n, total, s, k); break;
+    case 7: layers_of_slots<7>(off, n, total, s, k); break;
+    case 8: layers_of_slots<8>(off, n, total, s, k); break;
+    default: break;
+  }
+}
+
+// Minimum of v over the lanes j - back .. j of the wavefront (the lanes of lane j's run so far;
+// back <= lane), by DPP moves: shifts by 1, 2, 4 and 8 inside each row of 16 lanes, then the last
+// lane of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3. A lane takes a moved
+// value only when its source lies in its run. All 64 lanes must be active.
+__device__ __forceinline__ unsigned run_min_up(unsigned v, int back, int lane) {
+  constexpr int kNone = int(0xFFFFFFFFu);  // what a lane without a source receives; min identity
+  unsigned w;
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x111, 0xF, 0xF, false));  // row_shr:1
+  if (back >= 1) v = min(v, w);
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x112, 0xF, 0xF, false));  // row_shr:2
+  if (back >= 2) v = min(v, w);
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x114, 0xF, 0xF, false));  // row_shr:4
+  if (back >= 4) v = min(v, w);
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x118, 0xF, 0xF, false));  // row_shr:8
+  if (back >= 8) v = min(v, w);
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
+  if ((lane & 16) && back > (lane & 15)) v = min(v, w);
+  w = unsigned(__builtin_amdgcn_update_dpp(kNone, int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31
+  if (lane >= 32 && back >= lane - 31) v = min(v, w);
+  return v;
+}
+
 __device__ __forceinline__ float staged(const float *cb, int c0, uint32_t c) {
   return c < kTop ? cb[c0 + int(c)] : (c == kTop ? 0.0f : INFINITY);
 }
 
+// LDS of one tile of a wave kernel (narrow-only tiles need only the first members' storage)
+template <bool NARROW_ONLY>
+struct WaveLds {
+  float d[kTile];
+  int wcnt[kTile / 64];
+  // general-layer paths (one element in narrow-only instantiations)
+  std::conditional_t<NARROW_ONLY, int, GenTile> g;
+  // J_i shares and forced-row counts; with general layers they reuse the min-marginal words, which
+  // are read before the update begins (fewer LDS bytes per workgroup, more workgroups per CU)
+  float share_n[NARROW_ONLY ? kTile : 1];
+  int nf_n[NARROW_ONLY ? kTile : 1];
+  // flat path: the next levels' backward messages; in a forward tile, once the min-marginals are
+  // taken, the own levels' forward messages for the pull (one array serves both, so that more
+  // workgroups fit a CU's LDS)
+  float cb[NARROW_ONLY ? 1 : kFlatCap];
+};
+
+// One tile of a wave: tix indexes the pass's tile list (dir DIR), btix the backward tile of the same
+// levels (kWrap) or tix.
 // LIST: backward positions go through bwd_list (a wave that is not one contiguous layer range).
 // Narrow layers run one per lane. General layers (a level or its child level wider than 2) are
 // collected per tile and run either node-parallel over the whole tile (flat path) or by groups of
 // G lanes, as the tile's width class selects.
-template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
-__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0, const int bwd_tile0) {
-  __shared__ float s_d[kTile];
-  __shared__ int s_wcnt[kTile / 64];
-  // LDS of the general-layer paths (one element in narrow-only instantiations)
-  __shared__ std::conditional_t<NARROW_ONLY, int, GenTile> s_g;
-  // J_i shares and forced-row counts; with general layers they reuse the min-marginal words, which
-  // are read before the update begins (fewer LDS bytes per workgroup, more workgroups per CU)
-  __shared__ float s_share_n[NARROW_ONLY ? kTile : 1];
-  __shared__ int s_nf_n[NARROW_ONLY ? kTile : 1];
+// w0, end: the tile's start and end words (positions with the width class and root bits).
+// list: with LIST, whether this tile's positions go through bwd_list (callers that decide per tile
+// instantiate LIST true and pass the tile's flag; the wave launches leave it true).
+// COH: messages of this pass are read and written coherently (dataflow launch; see msg_ld).
+template <int DIR, int MODE, bool NARROW_ONLY, bool LIST, bool COH = false>
+__device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh, const int tix, const int btix,
+                                          const uint32_t w0, const uint32_t end, const bool list = true) {
+  float *const s_d = sh.d;
+  int *const s_wcnt = sh.wcnt;
+  auto &s_g = sh.g;
   float *s_share;
   int *s_nf;
   if constexpr (NARROW_ONLY) {
-    s_share = s_share_n;
-    s_nf = s_nf_n;
+    s_share = sh.share_n;
+    s_nf = sh.nf_n;
   } else {
     s_share = reinterpret_cast<float *>(s_g.m0);
     s_nf = reinterpret_cast<int *>(s_g.m1);
   }
-  // flat path: the next levels' backward messages; in a forward tile, once the min-marginals are
-  // taken, the own levels' forward messages for the pull (one array serves both, so that more
-  // workgroups fit a CU's LDS)
-  __shared__ float s_cb[NARROW_ONLY ? 1 : kFlatCap];
+  float *const s_cb = sh.cb;
   float *const s_fu = s_cb;
-  // flat path: the layer holding the first node of each 64-node chunk (own and next-level nodes)
-  const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
-  const int tix = tile0 + xcd_tile(int(blockIdx.x), int(gridDim.x));
-  const uint32_t w0 = uint32_t(tiles[2 * tix]);
   const int p0 = int(w0 & kTilePosMask);
   // a backward tile's end carries bit 31 when the tile holds a root level
-  const uint32_t end = uint32_t(tiles[2 * tix + 1]);
-  // kWrap: the same levels' backward tile (its root flag and bound partials)
-  const int btix = MODE == kWrap ? bwd_tile0 + (tix - tile0) : tix;
+  // kWrap: btix is the same levels' backward tile (its root flag and bound partials)
   const bool roots = (DIR == kBwd && (end & kTileRootBit) != 0u) ||
                      (MODE == kWrap && (uint32_t(D.bwd_tiles[2 * btix + 1]) & kTileRootBit) != 0u);
   const int cnt = int(end & ~kTileRootBit) - p0;
   const int s = int(threadIdx.x);
   const bool active = s < cnt;
 
-  Layer<DIR, NARROW_ONLY, false> ly;
+  Layer<DIR, NARROW_ONLY, false, COH> ly;
   ly.meta = 0;
   ly.lam0 = 0.0f;
   ly.m0 = ly.m1 = 0.0f;
@@ -326,7 +388,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
   int4 grec = make_int4(0, 0, 0, 0);
   int2 gnb = make_int2(-1, -1);
   if (active) {
-    const int L = (DIR == kBwd && LIST) ? D.bwd_list[p0 + s] : p0 + s;
+    const int L = (DIR == kBwd && LIST && list) ? D.bwd_list[p0 + s] : p0 + s;
     if (!NARROW_ONLY) {
       grec = D.grec[L];
       gnb = D.gnb[L];
@@ -401,18 +463,22 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     __syncthreads();
     if (flat) {
       // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
-      // t = s + r * kTile; slots past the tile's nodes are skipped per wavefront.
+      // t = s + r * kTile; slots past the tile's nodes are skipped per wavefront. The layers of all
+      // the lane's nodes are found first, together.
+      int ks[kFlatR], kcs[kFlatR];
+      slot_layers(T.wo, ngen, TW, s, ks);
+      slot_layers(T.co, ngen, TC, s, kcs);
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         kr[r] = -1;
         const int t = s + r * kTile;
         if (r * kTile < TW && t < TW) {
-          const int k = layer_of_node(T.wo, ngen, t);
+          const int k = ks[r];
           const int u = t - T.wo[k];
           kr[r] = k;
           ur[r] = u;
           ar[r] = D.garcs[T.os[k] + u];
-          fr[r] = D.mf[T.os[k] + u];
+          fr[r] = msg_ld<COH && DIR == kFwd>(D.mf + T.os[k] + u);
         }
       }
       // all loads of the lane first, then the LDS stores: a store right after its load would wait
@@ -425,9 +491,9 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         pkc[r] = kManyInArcs;
         cbr[r] = 0.0f;
         if (r * kTile < TC && t < TC) {
-          const int k = layer_of_node(T.co, ngen, t);
+          const int k = kcs[r];
           kc[r] = k;
-          cbr[r] = D.mbc[T.cs[k] + (t - T.co[k])];
+          cbr[r] = msg_ld<COH && DIR == kBwd>(D.mbc + T.cs[k] + (t - T.co[k]));
           if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];
         }
       }
@@ -440,26 +506,21 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
         if (r * kTile >= TW) break;
         const int k = kr[r];
         unsigned o0 = ord_of(INFINITY), o1 = o0;
-        int rest = 0;  // nodes of the same level on the following lanes
+        int rest = 0, back = 0;  // nodes of the same level on the following / preceding lanes
         if (k >= 0) {
           const int c0 = T.co[k];
           const float lam0 = T.lam[k];
           rest = (T.ww[k] & 0xFFFF) - 1 - ur[r];
+          back = min(ur[r], lane);
           o0 = ord_of(fr[r] + staged(s_cb, c0, ar[r] & 0xFFFFu));
           o1 = ord_of((fr[r] + lam0) + staged(s_cb, c0, ar[r] >> 16));
         }
         // segmented minimum over the runs of one level in the wavefront (a level's nodes sit on
-        // consecutive lanes), then one LDS atomic per run head instead of one per node; integer
-        // min of the order-preserving codes is exact
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const unsigned w0 = __shfl_down(o0, off, 64), w1 = __shfl_down(o1, off, 64);
-          if (lane + off < 64 && rest >= off) {
-            o0 = min(o0, w0);
-            o1 = min(o1, w1);
-          }
-        }
-        if (k >= 0 && (lane == 0 || ur[r] == 0)) {
+        // consecutive lanes), gathered at each run's last lane, then one LDS atomic per run instead
+        // of one per node; integer min of the order-preserving codes is exact
+        o0 = run_min_up(o0, back, lane);
+        o1 = run_min_up(o1, back, lane);
+        if (k >= 0 && (lane == 63 || rest == 0)) {
           atomicMin(&T.m0[k], o0);
           atomicMin(&T.m1[k], o1);
         }
@@ -467,7 +528,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     } else {
       const int grp = s / G, gl = s % G, ngrp = kTile / G;
       for (int k = grp; k < ngen; k += ngrp) {
-        const float2 mm = group_mm(D, T, k, gl, G);
+        const float2 mm = group_mm<DIR, COH>(D, T, k, gl, G);
         if (gl == 0) {
           T.m0[k] = ord_of(mm.x);
           T.m1[k] = ord_of(mm.y);
@@ -558,7 +619,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
             const int osc = T.osc[k];
             if (osc >= 0) {
               const int v = s + r * kTile - T.co[k], f0 = T.wo[k];
-              D.mf[osc + v] = pull_min_pk(D, pkc[r], T.rb[k], v, T.lam[k], [&](int u) { return s_fu[f0 + u]; });
+              msg_st<COH>(D.mf + osc + v, pull_min_pk(D, pkc[r], T.rb[k], v, T.lam[k], [&](int u) { return s_fu[f0 + u]; }));
             }
           }
         }
@@ -570,7 +631,7 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
           if (k >= 0) {
             const int u = s + r * kTile - T.wo[k], c0 = T.co[k], ps = T.pcs[k];
             const float v = fminf(staged(s_cb, c0, ar[r] & 0xFFFFu), staged(s_cb, c0, ar[r] >> 16) + T.lam[k]);
-            if (ps >= 0) D.mbc[ps + u] = v;
+            if (ps >= 0) msg_st<COH>(D.mbc + ps + u, v);
             if (u == 0) T.e[k] = v;
           }
         }
@@ -579,9 +640,9 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
       const int grp = s / G, gl = s % G, ngrp = kTile / G;
       for (int k = grp; k < ngen; k += ngrp) {
         if (DIR == kFwd) {
-          group_push(D, T, k, gl, G);
+          group_push<COH>(D, T, k, gl, G);
         } else {
-          const float r = group_bstep(D, T, k, gl, G);
+          const float r = group_bstep<COH>(D, T, k, gl, G);
           if (gl == 0) T.e[k] = r;
         }
       }
@@ -601,6 +662,151 @@ __global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile
     if (roots) {
       const double v = wave_sum(e);
       if ((threadIdx.x & 63) == 0) D.lbpart[kTile / 64 * tix + (int(threadIdx.x) >> 6)] = v;
+    }
+  }
+}
+
+// One wave: a workgroup per tile, tiles tile0 .. tile0 + gridDim.x - 1 (XCD-aware order).
+template <int DIR, int MODE, bool NARROW_ONLY, bool LIST>
+__global__ __launch_bounds__(kTile) void wave_kernel(const Dev D, const int tile0, const int bwd_tile0) {
+  __shared__ WaveLds<NARROW_ONLY> sh;
+  const int k = xcd_tile(int(blockIdx.x), int(gridDim.x));
+  const int tix = tile0 + k;
+  const int32_t *tiles = DIR == kFwd ? D.fwd_tiles : D.bwd_tiles;
+  wave_tile<DIR, MODE, NARROW_ONLY, LIST>(D, sh, tix, MODE == kWrap ? bwd_tile0 + k : tix, uint32_t(tiles[2 * tix]),
+                                          uint32_t(tiles[2 * tix + 1]));
+}
+
+// LDS of the dataflow pass kernel: the general layout when the plan has general layers (its narrow
+// tiles use the narrow layout in the same storage), else only the narrow one
+union WaveLdsMixed {
+  WaveLds<true> n;
+  WaveLds<false> g;
+};
+
+// Dataflow launch of one pass in update mode (Alg. "Min-marginal averaging", the forward or the
+// backward pass). Workgroups stay resident and take tiles in the pass's order (waves ascending); a
+// tile waits only for the tiles that write the messages it reads (the plan's dependency lists), not
+// for the whole previous wave, so independent rows and instances move on at their own pace.
+//
+// Tickets: the plan groups the instances (independent subproblems; one group for a single
+// instance) and every tile belongs to one group, as do the tiles it waits for. Each group's tiles
+// form a queue with a ticket counter of its own that hands out chunks of A.chunk consecutive tiles
+// of the queue in order (one counter for all would serialise every draw on one address).
+// Workgroup b starts at queue b mod n_queues and moves to the next queue when one runs dry; it
+// leaves when it has found every queue dry. Progress: within a queue, a tile waits only for
+// smaller tiles of the same queue, and when a chunk is drawn every smaller chunk of its queue has
+// been drawn, by a workgroup that runs. So the smallest unfinished tile of a queue either runs (all
+// it waits for is done, tiles of its own chunk before it included) or is still to be drawn while
+// every drawn chunk of its queue is done; then the queue's workgroups are free, or left for other
+// queues and come back, or others arrive as their own queues run dry. The waits thus end whatever
+// the residency. Each wait is bounded all the same: past spin_limit polls the workgroup sets the
+// error word and goes on, so the kernel always exits.
+//
+// Publication, per tile: the messages other tiles read are written and read with coherent
+// agent-scope accesses (msg_ld / msg_st), so no cache holds a stale copy of them and no cache
+// write-back or invalidation is needed. The workgroup waits until its own stores are complete
+// (vmcnt 0), then one lane stores the launch's generation to the tile's flag; a waiting workgroup
+// polls the flags with coherent loads, and its lanes read the messages only after the barrier that
+// follows the polls. Flags hold the generation of the launch that finished them (never reset, so a
+// launch never mistakes an older launch's flag for its own); the last workgroup to leave resets the
+// counters and advances the generation for the next launch of the pass.
+//
+// Tile records (32 bytes each): start word, end word, info (bit 0 narrow, bit 1 listed, bits 2-3
+// priority, bits 8-16 dependency count), offset of the dependency list, then up to four
+// dependencies inline (a tile with more reads them from the list).
+
+// wave issue priority 0..3 (s_setprio takes an immediate)
+__device__ __forceinline__ void set_priority(uint32_t p) {
+  switch (p) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+  }
+}
+
+template <int DIR, bool NARROW_PLAN>
+__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(NARROW_PLAN ? 8 : 6)))
+void pass_kernel(const Dev D, const PassArgs A) {
+  __shared__ std::conditional_t<NARROW_PLAN, WaveLds<true>, WaveLdsMixed> sh;
+  __shared__ int s_next;
+  const int s = int(threadIdx.x);
+  const uint32_t gen = A.ctl[kPassGen] + 1u;
+  int q = int(blockIdx.x) % A.n_queues, tried = 1;
+  auto counter = [&](int qq) { return A.ctl + kPassQueue0 + kPassQueueStride * qq; };
+  if (s == 0) s_next = int(atomicAdd(counter(q), 1u));
+  __syncthreads();
+  int k = s_next;
+  for (;;) {
+    int q0 = A.qptr[q], qn = A.qptr[q + 1] - q0;
+    // a dry queue: move on to the next one, leave once every queue was found dry
+    while (k * A.chunk >= qn) {
+      if (tried == A.n_queues) break;
+      q = q + 1 == A.n_queues ? 0 : q + 1;
+      ++tried;
+      __syncthreads();
+      if (s == 0) s_next = int(atomicAdd(counter(q), 1u));
+      __syncthreads();
+      k = s_next;
+      q0 = A.qptr[q];
+      qn = A.qptr[q + 1] - q0;
+    }
+    if (k * A.chunk >= qn) break;
+    // the next chunk of this queue is drawn now and read after this one (both drawn in order, so
+    // the argument above still holds)
+    int nxt = 0;
+    if (s == 0) nxt = int(atomicAdd(counter(q), 1u));
+    const int j1 = min(qn, (k + 1) * A.chunk);
+    for (int j = k * A.chunk; j < j1; ++j) {
+      const int t = A.qtile[q0 + j];
+      const int4 ra = A.trec[2 * t], rb = A.trec[2 * t + 1];
+      const uint32_t info = uint32_t(ra.z);
+      const int nd = int((info >> 8) & 0x1FFu);
+      if (nd) {
+        if (s < 64) {
+          for (int e = s; e < nd; e += 64) {
+            const int u = nd <= 4 ? (e == 0 ? rb.x : (e == 1 ? rb.y : (e == 2 ? rb.z : rb.w))) : A.dep_list[ra.w + e];
+            const uint32_t *f = A.flags + u;
+            uint32_t spins = 0u;
+            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+              if (++spins > A.spin_limit) {
+                atomicOr(A.ctl + kPassErr, 1u);
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+            }
+          }
+        }
+        // the polls returned before any lane passes the barrier; the messages are then read with
+        // coherent loads (no cache holds a stale copy for them to hit)
+        __syncthreads();
+      }
+      const bool list = (info & 2u) != 0u;
+      set_priority((info >> 2) & 3u);
+      if constexpr (NARROW_PLAN) {
+        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+      } else if (info & 1u) {
+        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+      } else {
+        wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+      }
+      // every lane's coherent message stores of the tile complete (vmcnt 0; expcnt and lgkmcnt at
+      // their maximum) before one lane stores the tile's flag; the barrier also frees the LDS
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+      if (s == 0) __hip_atomic_store(A.flags + t, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (s == 0) s_next = nxt;
+    __syncthreads();
+    k = s_next;
+  }
+  if (s == 0) {
+    const uint32_t gone = __hip_atomic_fetch_add(A.ctl + kPassGone, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (gone == gridDim.x - 1u) {
+      for (int qq = 0; qq < A.n_queues; ++qq) __hip_atomic_store(counter(qq), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(A.ctl + kPassGone, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(A.ctl + kPassGen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -918,6 +1124,26 @@ hipError_t launch_wave(int dir, int mode, bool narrow_only, bool list, int nt, i
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
+}
+
+template <int DIR, bool NARROW_PLAN>
+static hipError_t pass_dispatch(int grid, const Dev &D, const PassArgs &A, hipStream_t s) {
+  hipLaunchKernelGGL((pass_kernel<DIR, NARROW_PLAN>), dim3(grid), dim3(kTile), 0, s, D, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(int dir, bool narrow_plan, int grid, const Dev &D, const PassArgs &A, hipStream_t s) {
+  if (grid <= 0 || A.n_tiles <= 0) return hipSuccess;
+  if (dir == kFwd) return narrow_plan ? pass_dispatch<kFwd, true>(grid, D, A, s) : pass_dispatch<kFwd, false>(grid, D, A, s);
+  return narrow_plan ? pass_dispatch<kBwd, true>(grid, D, A, s) : pass_dispatch<kBwd, false>(grid, D, A, s);
+}
+
+hipError_t pass_blocks_per_cu(int dir, bool narrow_plan, int *blocks) {
+  const void *fn = dir == kFwd ? (narrow_plan ? reinterpret_cast<const void *>(pass_kernel<kFwd, true>)
+                                              : reinterpret_cast<const void *>(pass_kernel<kFwd, false>))
+                               : (narrow_plan ? reinterpret_cast<const void *>(pass_kernel<kBwd, true>)
+                                              : reinterpret_cast<const void *>(pass_kernel<kBwd, false>));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kTile, 0);
 }
 
 template <int DIR, int MODE>

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 
 #include "internal.h"
@@ -97,15 +98,17 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile and
-// their general levels hold at most cap nodes (wwork: per variable); a variable with
-// more rows than kTile gets a big tile of its own. Tiles are (start, end) pairs.
+// Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile, their
+// general levels hold at most cap nodes (wwork: per variable) and they belong to the same group of
+// instances (grp); a variable with more rows than kTile gets a big tile of its own. Tiles are
+// (start, end) pairs.
 void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj, const std::vector<int64_t> &wwork,
-               int64_t cap, int64_t pos0, std::vector<int32_t> &tiles, std::vector<int32_t> &big, WaveRange &wr) {
+               const std::vector<int32_t> &grp, int64_t cap, int64_t pos0, std::vector<int32_t> &tiles,
+               std::vector<int32_t> &big, WaveRange &wr) {
   wr.tile_begin = int32_t(tiles.size() / 2);
   wr.big_begin = int32_t(big.size() / 2);
   int64_t pos = pos0, start = pos0, work = 0;
-  int32_t cnt = 0;
+  int32_t cnt = 0, g = -1;
   for (int32_t i : vars) {
     const int32_t c = nj[i];
     if (c > kTile) {
@@ -118,7 +121,7 @@ void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj,
       work = 0;
       continue;
     }
-    if (cnt + c > kTile || (cnt && work + wwork[i] > cap)) {
+    if (cnt + c > kTile || (cnt && work + wwork[i] > cap) || (cnt && grp[i] != g)) {
       tiles.push_back(int32_t(start));
       tiles.push_back(int32_t(pos));
       start = pos;
@@ -128,6 +131,7 @@ void tile_pass(const std::vector<int32_t> &vars, const std::vector<int32_t> &nj,
     pos += c;
     cnt += c;
     work += wwork[i];
+    g = grp[i];
   }
   if (cnt) { tiles.push_back(int32_t(start)); tiles.push_back(int32_t(pos)); }
   wr.tile_end = int32_t(tiles.size() / 2);
@@ -273,6 +277,80 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
       }
     for (int64_t L = 0; L < I; ++L)
       if (!seen[L]) return "layer missing from a pass";
+  }
+  // dataflow launch: every dependency tile has a smaller index than the tile waiting for it (so it
+  // was taken by a running workgroup before, and the wait ends), and covers the writer of each
+  // message the tile reads
+  if (P.pers_ok) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;
+      const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+      const auto &ptr = pass ? P.bdep_ptr : P.fdep_ptr;
+      const auto &lst = pass ? P.bdep_list : P.fdep_list;
+      const auto &info = pass ? P.btinfo : P.ftinfo;
+      const size_t nt = tiles.size() / 2;
+      if (ptr.size() != nt + 1 || info.size() != nt || ptr[0] != 0 || size_t(ptr[nt]) != lst.size()) return "dependency arrays";
+      std::vector<int32_t> tile_of(size_t(I), -1);
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+          if (((info[size_t(t)] >> 1) & 1u) != uint32_t(pass && wr.list)) return "tile info list bit";
+          const int64_t p0 = uint32_t(tiles[2 * size_t(t)]) & kTilePosMask;
+          const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          for (int64_t q = p0; q < p1; ++q) tile_of[size_t((pass && wr.list) ? P.bwd_list[size_t(q)] : q)] = t;
+        }
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+          const int32_t d0 = ptr[size_t(t)], d1 = ptr[size_t(t) + 1];
+          if (d1 < d0) return "dependency offsets";
+          for (int32_t q = d0; q < d1; ++q)
+            if (lst[size_t(q)] < 0 || lst[size_t(q)] >= t || (q > d0 && lst[size_t(q)] <= lst[size_t(q) - 1]))
+              return "dependency tile not smaller than its waiter";
+          const int64_t p0 = uint32_t(tiles[2 * size_t(t)]) & kTilePosMask;
+          const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          bool narrow = true;
+          for (int64_t q = p0; q < p1; ++q) {
+            const int64_t L = (pass && wr.list) ? P.bwd_list[size_t(q)] : q;
+            narrow = narrow && ((P.meta[size_t(L)] >> kMetaWidthShift) & 3u) != 0u;
+            const int32_t nb = pass ? P.child[size_t(L)] : P.parent[size_t(L)];
+            if (nb >= 0 && !std::binary_search(lst.begin() + d0, lst.begin() + d1, tile_of[size_t(nb)]))
+              return "missing dependency";
+          }
+          if ((info[size_t(t)] & 1u) != (narrow ? 1u : 0u)) return "tile info narrow bit";
+          const auto &rec = pass ? P.btrec : P.ftrec;
+          const int32_t *r = rec.data() + 8 * size_t(t);
+          const int32_t nd = d1 - d0;
+          if (rec.size() != 8 * nt || r[0] != tiles[2 * size_t(t)] || r[1] != tiles[2 * size_t(t) + 1] ||
+              uint32_t(r[2]) != (info[size_t(t)] | (uint32_t(nd) << 8)) || r[3] != d0 || nd >= 512)
+            return "tile record";
+          for (int32_t q = 0; q < 4; ++q)
+            if (r[4 + q] != (q < nd ? lst[size_t(d0 + q)] : -1)) return "tile record dependencies";
+        }
+      // queues: every tile in exactly one, ascending; a tile's layers and its dependencies all in the
+      // queue's group
+      const auto &qptr = pass ? P.bqptr : P.fqptr;
+      const auto &qtile = pass ? P.bqtile : P.fqtile;
+      if (P.n_groups < 1 || P.n_groups > kPassQueues || qptr.size() != size_t(P.n_groups) + 1 || qptr[0] != 0 ||
+          size_t(qptr.back()) != nt || qtile.size() != nt)
+        return "queue arrays";
+      std::vector<int32_t> tq(nt, -1);
+      for (int32_t g = 0; g < P.n_groups; ++g)
+        for (int32_t k = qptr[size_t(g)]; k < qptr[size_t(g) + 1]; ++k) {
+          const int32_t t = qtile[size_t(k)];
+          if (t < 0 || size_t(t) >= nt || tq[size_t(t)] >= 0 || (k > qptr[size_t(g)] && t <= qtile[size_t(k) - 1]))
+            return "queue tiles";
+          tq[size_t(t)] = g;
+        }
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+          const int64_t p0 = uint32_t(tiles[2 * size_t(t)]) & kTilePosMask;
+          const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+          for (int64_t q = p0; q < p1; ++q)
+            if (P.var_group[size_t(P.layer_var[size_t((pass && wr.list) ? P.bwd_list[size_t(q)] : q)])] != tq[size_t(t)])
+              return "tile spans groups";
+          for (int32_t q = ptr[size_t(t)]; q < ptr[size_t(t) + 1]; ++q)
+            if (tq[size_t(lst[size_t(q)])] != tq[size_t(t)]) return "dependency across groups";
+        }
+    }
   }
   for (int32_t j = 0; j < P.m; ++j)
     if (P.root_slot[j] >= S || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
@@ -560,7 +638,31 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.Db = std::max(P.Db, t + 1);
   }
 
-  // Storage order. Each forward wave sorts its variables by backward wave, then by the storage
+  // Groups of instances for the dataflow launch: instances never share a row, so a tile whose
+  // layers all belong to one group depends only on tiles of that group; each group gets a ticket
+  // queue of its own. Up to kPassQueues groups of about equal node counts (largest instance first
+  // into the lightest group); a single instance is one group.
+  P.var_group.assign(size_t(n), 0);
+  P.n_groups = 1;
+  if (p.inst_var.size() > 2) {
+    const size_t ni = p.inst_var.size() - 1;
+    std::vector<int64_t> inst_nodes(ni, 0);
+    for (size_t k = 0; k < ni; ++k)
+      for (int64_t j = p.inst_row[k]; j < p.inst_row[k + 1]; ++j)
+        if (P.row_shape[size_t(j)] >= 0) inst_nodes[k] += int64_t(P.shapes[size_t(P.row_shape[size_t(j)])].lo.size());
+    std::vector<int32_t> by_size(ni);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) { return inst_nodes[size_t(a)] > inst_nodes[size_t(b)]; });
+    P.n_groups = int32_t(std::min<size_t>(ni, size_t(kPassQueues)));
+    std::vector<int64_t> load(size_t(P.n_groups), 0);
+    for (int32_t k : by_size) {
+      const int32_t g = int32_t(std::min_element(load.begin(), load.end()) - load.begin());
+      load[size_t(g)] += inst_nodes[size_t(k)];
+      for (int64_t i = p.inst_var[size_t(k)]; i < p.inst_var[size_t(k) + 1]; ++i) P.var_group[size_t(i)] = g;
+    }
+  }
+
+  // Storage order. Each forward wave sorts its variables by group of instances, then by backward wave, then by the storage
   // position of their earliest parent layer (the previous level of one of their rows), ties and
   // parentless variables by processing order. A workgroup's layers then push to and read from
   // next-level slots that sit together, instead of cache lines shared with other workgroups (and
@@ -579,7 +681,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   P.var_first.assign(size_t(n), -1);
   std::vector<uint32_t> segpos(size_t(I), 0);
   int64_t L = 0;
-  std::vector<std::pair<int64_t, int32_t>> keyed;
+  std::vector<std::tuple<int32_t, int64_t, int32_t>> keyed;
   for (int32_t t = 1; t <= P.Df; ++t) {
     keyed.clear();
     for (int32_t i : fw[t]) {
@@ -590,10 +692,11 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       }
       // first by backward wave, so that each backward wave's members sit in runs inside each forward
       // wave (the backward pass gathers them through the index list with fewer partial cache lines)
-      keyed.emplace_back((int64_t(P.wave_b[i]) << 40) + (key == INT64_MAX ? (int64_t(1) << 40) - 1 : key), P.rank[i]);
+      keyed.emplace_back(P.var_group[size_t(i)], (int64_t(P.wave_b[i]) << 40) + (key == INT64_MAX ? (int64_t(1) << 40) - 1 : key),
+                         P.rank[i]);
     }
     std::sort(keyed.begin(), keyed.end());
-    for (size_t q0 = 0; q0 < keyed.size(); ++q0) fw[t][q0] = P.order[keyed[q0].second];
+    for (size_t q0 = 0; q0 < keyed.size(); ++q0) fw[t][q0] = P.order[std::get<2>(keyed[q0])];
     for (int32_t i : fw[t]) {
       P.var_first[i] = int32_t(L);
       for (int64_t q = iptr[i]; q < iptr[i + 1]; ++q, ++L) {
@@ -605,10 +708,14 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       }
     }
   }
-  // a backward wave lists its variables in storage order, so that a backward wave holding the
-  // same variables as a forward wave is one contiguous layer range
+  // a backward wave lists its variables by group, then in storage order, so that a backward wave
+  // holding the same variables as a forward wave is one contiguous layer range (one group) and a
+  // group's variables sit together in its tiles
   for (int32_t t = 1; t <= P.Db; ++t)
-    std::sort(bw[t].begin(), bw[t].end(), [&](int32_t x, int32_t y) { return P.var_first[x] < P.var_first[y]; });
+    std::sort(bw[t].begin(), bw[t].end(), [&](int32_t x, int32_t y) {
+      return P.var_group[size_t(x)] != P.var_group[size_t(y)] ? P.var_group[size_t(x)] < P.var_group[size_t(y)]
+                                                              : P.var_first[x] < P.var_first[y];
+    });
 
   // node slots: a level of at most 2 nodes sits at slots 2L, 2L+1 (the second one padding when it
   // has one node); wider levels follow after 2I, in layer order
@@ -818,7 +925,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       }
   };
   for (int32_t t = 1; t <= P.Df; ++t) {
-    tile_pass(fw[t], P.var_nj, wwork, P.tile_work, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
+    tile_pass(fw[t], P.var_nj, wwork, P.var_group, P.tile_work, pos, P.fwd_tiles, P.fwd_big, P.fwd_waves[t - 1]);
     P.fwd_waves[t - 1].list = 0;
     wave_work(fw[t], P.fwd_waves[t - 1]);
     for (int32_t i : fw[t]) pos += P.var_nj[i];
@@ -837,7 +944,8 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         if (P.bwd_list[pos] != P.bwd_list[w0] + (pos - w0)) contig = false;
       }
     WaveRange &wr = P.bwd_waves[t - 1];
-    tile_pass(bw[t], P.var_nj, wwork, P.tile_work, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big, wr);
+    tile_pass(bw[t], P.var_nj, wwork, P.var_group, P.tile_work, contig ? P.bwd_list[w0] : w0, P.bwd_tiles, P.bwd_big,
+              wr);
     wr.list = contig ? 0 : 1;
     wave_work(bw[t], wr);
     P.bwd_contiguous = P.bwd_contiguous && contig;
@@ -909,6 +1017,96 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         tiles[2 * size_t(t)] = int32_t(uint32_t(tiles[2 * size_t(t)]) | (cls << kTileClsShift));
         if (mw > 0) P.class_tiles[cls]++;
       }
+  }
+
+  // dataflow launch: each tile waits only for the tiles that write what it reads. In the forward
+  // pass a layer reads its own level's forward messages, pushed by its parent layer; in the
+  // backward pass its child level's backward messages, written by its child layer's backward step.
+  // Everything else a tile reads (multipliers of its own layers, the other pass's messages, the
+  // structure) is written before the pass begins.
+  P.pers_ok = P.fwd_big.empty() && P.bwd_big.empty();
+  P.fdep_ptr.clear();
+  P.fdep_list.clear();
+  P.bdep_ptr.clear();
+  P.bdep_list.clear();
+  P.ftinfo.clear();
+  P.btinfo.clear();
+  if (P.pers_ok) {
+    std::vector<int32_t> tile_of(In0, -1), d;
+    for (int pass = 0; pass < 2; ++pass) {
+      const auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;
+      const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+      auto &ptr = pass ? P.bdep_ptr : P.fdep_ptr;
+      auto &lst = pass ? P.bdep_list : P.fdep_list;
+      auto &info = pass ? P.btinfo : P.ftinfo;
+      const size_t nt = tiles.size() / 2;
+      auto layer_at = [&](const WaveRange &wr, int64_t q) { return (pass && wr.list) ? int64_t(P.bwd_list[size_t(q)]) : q; };
+      auto span = [&](int32_t t) {
+        return std::make_pair(int64_t(uint32_t(tiles[2 * size_t(t)]) & kTilePosMask),
+                              int64_t(uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit));
+      };
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t)
+          for (int64_t q = span(t).first; q < span(t).second; ++q) tile_of[size_t(layer_at(wr, q))] = t;
+      ptr.assign(nt + 1, 0);
+      info.assign(nt, 0u);
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+          d.clear();
+          bool narrow = true;
+          for (int64_t q = span(t).first; q < span(t).second; ++q) {
+            const int64_t Lq = layer_at(wr, q);
+            const int32_t nb = pass ? P.child[size_t(Lq)] : P.parent[size_t(Lq)];
+            if (nb >= 0) d.push_back(tile_of[size_t(nb)]);
+            narrow = narrow && ((P.meta[size_t(Lq)] >> kMetaWidthShift) & 3u) != 0u;
+          }
+          std::sort(d.begin(), d.end());
+          d.erase(std::unique(d.begin(), d.end()), d.end());
+          lst.insert(lst.end(), d.begin(), d.end());
+          ptr[size_t(t) + 1] = int32_t(lst.size());
+          info[size_t(t)] = (narrow ? 1u : 0u) | (wr.list ? 2u : 0u);
+        }
+      // issue priority from the slack of each tile on the pass's dependency graph: the longest chain
+      // of tiles through it against the longest chain of the pass. Tiles on (or near) the longest
+      // chains run at a higher wave priority, so their latency, which sets the pass's length, is
+      // less inflated by the other workgroups sharing their compute unit.
+      std::vector<int32_t> depth(nt, 1), height(nt, 1);
+      for (size_t t = 0; t < nt; ++t)
+        for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q) depth[t] = std::max(depth[t], depth[size_t(lst[size_t(q)])] + 1);
+      for (size_t t = nt; t-- > 0;)
+        for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q)
+          height[size_t(lst[size_t(q)])] = std::max(height[size_t(lst[size_t(q)])], height[t] + 1);
+      int32_t longest = 0;
+      for (size_t t = 0; t < nt; ++t) longest = std::max(longest, depth[t] + height[t] - 1);
+      for (size_t t = 0; t < nt; ++t) {
+        const int32_t slack = longest - (depth[t] + height[t] - 1);
+        const uint32_t prio = slack <= 1 ? 3u : (slack <= 4 ? 2u : (slack <= 16 ? 1u : 0u));
+        info[t] |= prio << 2;
+      }
+      // the group's queue: its tiles in pass order
+      auto &qptr = pass ? P.bqptr : P.fqptr;
+      auto &qtile = pass ? P.bqtile : P.fqtile;
+      std::vector<int32_t> tgroup(nt, 0);
+      for (const WaveRange &wr : waves)
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t)
+          tgroup[size_t(t)] = P.var_group[size_t(P.layer_var[size_t(layer_at(wr, span(t).first))])];
+      qptr.assign(size_t(P.n_groups) + 1, 0);
+      for (size_t t = 0; t < nt; ++t) qptr[size_t(tgroup[t]) + 1]++;
+      for (int32_t g = 0; g < P.n_groups; ++g) qptr[size_t(g) + 1] += qptr[size_t(g)];
+      qtile.assign(nt, 0);
+      std::vector<int32_t> fill(qptr.begin(), qptr.end() - 1);
+      for (size_t t = 0; t < nt; ++t) qtile[size_t(fill[size_t(tgroup[t])]++)] = int32_t(t);
+      auto &rec = pass ? P.btrec : P.ftrec;
+      rec.assign(8 * nt, -1);
+      for (size_t t = 0; t < nt; ++t) {
+        const int32_t nd = ptr[t + 1] - ptr[t];
+        rec[8 * t] = tiles[2 * t];
+        rec[8 * t + 1] = tiles[2 * t + 1];
+        rec[8 * t + 2] = int32_t(info[t] | (uint32_t(nd) << 8));
+        rec[8 * t + 3] = ptr[t];
+        for (int32_t q = 0; q < std::min(nd, 4); ++q) rec[8 * t + 4 + q] = lst[size_t(ptr[t] + q)];
+      }
+    }
   }
 
   P.lb_const = 0.0;
@@ -1013,6 +1211,17 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.inst_cut = take(4 * P.inst_cut.size());
   A.inst_cut_idx = take(4 * P.inst_cut_idx.size());
   A.exit_rec = take(4 * P.exit_rec.size());
+  A.fdep_list = take(4 * P.fdep_list.size());
+  A.bdep_list = take(4 * P.bdep_list.size());
+  A.ftrec = take(4 * P.ftrec.size());
+  A.btrec = take(4 * P.btrec.size());
+  A.fqptr = take(4 * P.fqptr.size());
+  A.fqtile = take(4 * P.fqtile.size());
+  A.bqptr = take(4 * P.bqptr.size());
+  A.bqtile = take(4 * P.bqtile.size());
+  A.fflag = take(4 * P.ftinfo.size());
+  A.bflag = take(4 * P.btinfo.size());
+  A.pctl = take(4 * 2 * size_t(kPassCtlWords));
   A.total = off;
   const std::string bad = validate_layout(P, ownw, childw, level, exit_cut, root_cut);
   if (!bad.empty()) return set_error(BDDMP_INVALID_ARG, "internal layout check failed: " + bad);

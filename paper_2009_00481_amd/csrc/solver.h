@@ -25,6 +25,8 @@ int32_t solver_set_lambda(Solver &S, const float *lam);
 int32_t solver_copy_duals(Solver &S, bool out, float *mu_bar, float *mu, float *dfw, float *dbw);
 int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj, int64_t *nviol);
 int32_t solver_set_graphs(Solver &S, int32_t enable);
+int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk);
+int32_t solver_get_launch(const Solver &S, int32_t *mode, int32_t *chunk);
 int32_t solver_set_groups(Solver &S, const int32_t *lanes);
 int32_t solver_get_groups(const Solver &S, int32_t *lanes);
 int32_t solver_autotune(Solver &S, int32_t iters, int32_t *lanes);

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <initializer_list>
 #include <mutex>
 #include <string>
@@ -38,6 +39,11 @@ struct Solver {
   hipGraphExec_t gexec = nullptr, gexec_wrap = nullptr;
   uint32_t graph_gsel = 0;
   bool costs_replaced = false;  // bddmp_solver_set_costs was called (instance constants are stale)
+  // dataflow launch of the update passes (one launch per pass, see pass_kernel): on or off, the
+  // arguments per pass (forward, backward) and the resident grid
+  bool dataflow = false;
+  PassArgs pass[2]{};
+  int pass_grid[2] = {0, 0};
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gexec_wrap) (void)hipGraphExecDestroy(gexec_wrap);
@@ -58,6 +64,22 @@ int32_t hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 int32_t launched(hipError_t e, const char *what) { return e == hipSuccess ? BDDMP_OK : hip_fail(e, what); }
+
+// polls of one dependency flag before a wait of the dataflow launch gives up (each poll is a load
+// and a short sleep, about a microsecond: several seconds in all, far beyond any real wait)
+constexpr uint32_t kPassSpinLimit = 1u << 23;
+
+// BDDMP_DEVICE if a dataflow launch gave up a wait (its error word is set; the stream is
+// synchronised by the caller before *err is read)
+int32_t pass_error(uint32_t err) {
+  if (!err) return BDDMP_OK;
+  return set_error(BDDMP_DEVICE, "a dependency wait of the dataflow pass launch exceeded its bound; the results since the "
+                                 "last reset are invalid");
+}
+
+// the turnaround and wrap-around launches fuse wave launches; the dataflow launch has none
+bool use_turn(const Solver &S) { return S.plan->fuse_turn && !S.dataflow; }
+bool use_wrap(const Solver &S) { return S.plan->fuse_wrap && !S.dataflow; }
 
 // NONFINITE unless every value of the device arrays (float or double, n each) is finite; checked on
 // the device, then the stream is synchronised to read the result.
@@ -117,6 +139,12 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
   const size_t w0 = (skip_first && dir == kFwd) ? 1 : 0;
   Timer tm{ev};
   if (int32_t rc = tm.start(st, dir)) return rc;
+  if (S.dataflow && mode == kUpdate) {
+    const int p = dir == kFwd ? 0 : 1;
+    if (int32_t rc = launched(launch_pass(dir, P.n_general == 0, S.pass_grid[p], S.D, S.pass[p], st), "pass kernel"))
+      return rc;
+    return tm.stop(st, S.pass[p].n_tiles > 0 ? 1 : 0);
+  }
   for (size_t w = w0; w < nw; ++w) {
     const WaveRange &wr = waves[w];
     const int nt = wr.tile_end - wr.tile_begin;
@@ -173,9 +201,9 @@ int32_t initial_sweep(Solver &S) {
 // wrap-around launch, form 2 starts at the second forward wave and ends with the plain last wave.
 int32_t enqueue_iteration(Solver &S, std::vector<EventPair> *ev, hipStream_t st, int form = 0) {
   const Plan &P = *S.plan;
-  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st, P.fuse_turn, form != 0)) return rc;
+  if (int32_t rc = run_pass(S, kFwd, kUpdate, ev, st, use_turn(S), form != 0)) return rc;
   if (int32_t rc = launched(launch_copy_fwd(S.D, int(P.n_cuts), int(P.n_cut_narrow), st), "copy-arc update")) return rc;
-  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st, P.fuse_turn, false, form == 1)) return rc;
+  if (int32_t rc = run_pass(S, kBwd, kUpdate, ev, st, use_turn(S), false, form == 1)) return rc;
   if (int32_t rc = enqueue_copy_bwd(S, 1, st)) return rc;
   return enqueue_lb(S, ev, st);
 }
@@ -219,7 +247,7 @@ int32_t capture_form(Solver &S, int form, hipGraphExec_t &out) {
 // enqueue_iteration that runs of iterations are made of.
 int32_t capture_iteration(Solver &S) {
   drop_graph(S);
-  const bool wrap = S.plan->fuse_wrap;
+  const bool wrap = use_wrap(S);
   if (int32_t rc = capture_form(S, wrap ? 2 : 0, S.gexec)) return rc;
   if (wrap)
     if (int32_t rc = capture_form(S, 1, S.gexec_wrap)) {
@@ -299,6 +327,19 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.inst_cut_idx = reinterpret_cast<const int32_t *>(b + A.inst_cut_idx);
   D.exit_rec = P.exit_rec.empty() ? nullptr : reinterpret_cast<const int32_t *>(b + A.exit_rec);
   D.gamma = P.split_gamma;
+  for (int p = 0; p < 2; ++p) {
+    PassArgs &pa = S->pass[p];
+    pa.trec = reinterpret_cast<const int4 *>(b + (p ? A.btrec : A.ftrec));
+    pa.dep_list = reinterpret_cast<const int32_t *>(b + (p ? A.bdep_list : A.fdep_list));
+    pa.qptr = reinterpret_cast<const int32_t *>(b + (p ? A.bqptr : A.fqptr));
+    pa.qtile = reinterpret_cast<const int32_t *>(b + (p ? A.bqtile : A.fqtile));
+    pa.n_queues = P.n_groups;
+    pa.flags = reinterpret_cast<uint32_t *>(b + (p ? A.bflag : A.fflag));
+    pa.ctl = reinterpret_cast<uint32_t *>(b + A.pctl) + kPassCtlWords * p;
+    pa.n_tiles = int32_t((p ? P.btinfo : P.ftinfo).size());
+    pa.chunk = 1;
+    pa.spin_limit = kPassSpinLimit;
+  }
 
   auto up = [&](size_t off, const void *src, size_t nbytes) -> hipError_t {
     if (!nbytes) return hipSuccess;
@@ -336,11 +377,26 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.inst_cut_idx, P.inst_cut_idx.data(), 4 * P.inst_cut_idx.size()),
       up(A.exit_rec, P.exit_rec.data(), 4 * P.exit_rec.size()),
       up(A.cut_arc, P.cut_arc.data(), 2 * P.cut_arc.size()),
+      up(A.fdep_list, P.fdep_list.data(), 4 * P.fdep_list.size()),
+      up(A.bdep_list, P.bdep_list.data(), 4 * P.bdep_list.size()),
+      up(A.ftrec, P.ftrec.data(), 4 * P.ftrec.size()),
+      up(A.btrec, P.btrec.data(), 4 * P.btrec.size()),
+      up(A.fqptr, P.fqptr.data(), 4 * P.fqptr.size()),
+      up(A.fqtile, P.fqtile.data(), 4 * P.fqtile.size()),
+      up(A.bqptr, P.bqptr.data(), 4 * P.bqptr.size()),
+      up(A.bqtile, P.bqtile.data(), 4 * P.bqtile.size()),
   };
   for (hipError_t e : errs)
     if (e != hipSuccess) {
       delete S;
       return hip_fail(e, "hipMemcpyAsync (upload)");
+    }
+  // dataflow launch state: flags and control words start at zero (generation 0, no launch yet)
+  for (const auto &z : {std::make_pair(A.fflag, P.ftinfo.size()), std::make_pair(A.bflag, P.btinfo.size()),
+                        std::make_pair(A.pctl, 2 * size_t(kPassCtlWords))})
+    if (int32_t rc = launched(launch_fill(reinterpret_cast<float *>(b + z.first), 0.0f, int(z.second), S->stream), "fill")) {
+      delete S;
+      return rc;
     }
   if (const int32_t rc = solver_reset(*S)) {
     delete S;
@@ -366,6 +422,10 @@ int32_t solver_reset(Solver &S) {
   const int nlb = int(2 * (P.n_lbpart + P.n_cut_parts + 1));
   if (int32_t rc = launched(launch_fill(reinterpret_cast<float *>(S.D.lbpart), 0.0f, nlb, S.stream), "fill")) return rc;
   if (int32_t rc = launched(launch_set_counter(S.D, S.n_hist, S.stream), "set_counter")) return rc;
+  // the dataflow launches' error words (generations and tickets stay as they are)
+  for (int p = 0; p < 2; ++p)
+    if (int32_t rc = launched(launch_fill(reinterpret_cast<float *>(S.pass[p].ctl + kPassErr), 0.0f, 1, S.stream), "fill"))
+      return rc;
   if (int32_t rc = launched(launch_free_const(S.D, P.n, 1.0f, S.stream), "free_const")) return rc;
   S.iters = 0;
   return initial_sweep(S);
@@ -375,9 +435,10 @@ int32_t solver_iterate(Solver &S, int32_t n) {
   if (n < 0) return set_error(BDDMP_INVALID_ARG, "negative iteration count");
   if (S.use_graph && n > 0) {
     const Plan &P = *S.plan;
-    if (!S.gexec || (P.fuse_wrap && !S.gexec_wrap) || S.graph_gsel != S.D.gsel)
+    const bool wrap = use_wrap(S);
+    if (!S.gexec || (wrap && !S.gexec_wrap) || S.graph_gsel != S.D.gsel)
       if (int32_t rc = capture_iteration(S)) return rc;
-    if (P.fuse_wrap) {
+    if (wrap) {
       // the first forward wave, then n - 1 iterations that end one wave into the next, then one
       // that ends with the plain last backward wave
       const WaveRange &f = P.fwd_waves.front();
@@ -387,7 +448,7 @@ int32_t solver_iterate(Solver &S, int32_t n) {
         return rc;
     }
     for (int32_t t = 0; t < n; ++t) {
-      HIP_TRY(hipGraphLaunch((P.fuse_wrap && t + 1 < n) ? S.gexec_wrap : S.gexec, S.stream), "hipGraphLaunch");
+      HIP_TRY(hipGraphLaunch((wrap && t + 1 < n) ? S.gexec_wrap : S.gexec, S.stream), "hipGraphLaunch");
       S.n_hist++;
       S.iters++;
     }
@@ -436,11 +497,15 @@ int32_t solver_lower_bound(Solver &S, double *lb, double *residual, double *any_
   double h = 0.0, sc[2] = {0.0, 0.0};
   const int slot = int((S.n_hist - 1) % P.hist_cap);
   HIP_TRY(hipMemcpyAsync(&h, S.D.lb_hist + slot, 8, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
+  uint32_t err[2] = {0u, 0u};
+  for (int p = 0; p < 2; ++p)
+    HIP_TRY(hipMemcpyAsync(err + p, S.pass[p].ctl + kPassErr, 4, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
   if ((residual || any_lambda_bound) && P.n > 0) {
     if (int32_t rc = launched(launch_residual(S.D, P.n, S.stream), "residual")) return rc;
     HIP_TRY(hipMemcpyAsync(sc, S.D.scal, 16, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
   }
   HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
+  if (int32_t rc = pass_error(err[0] | err[1])) return rc;
   if (lb) *lb = h;
   if (residual) *residual = sc[0];
   if (any_lambda_bound) *any_lambda_bound = h + sc[1];
@@ -468,7 +533,11 @@ int32_t solver_lb_history(Solver &S, double *out, int32_t cap, int32_t *n_out) {
   std::vector<double> ring(size_t(P.hist_cap));
   HIP_TRY(hipMemcpyAsync(ring.data(), S.D.lb_hist, 8 * size_t(P.hist_cap), hipMemcpyDeviceToHost, S.stream),
           "hipMemcpyAsync");
+  uint32_t err[2] = {0u, 0u};
+  for (int p = 0; p < 2; ++p)
+    HIP_TRY(hipMemcpyAsync(err + p, S.pass[p].ctl + kPassErr, 4, hipMemcpyDeviceToHost, S.stream), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
+  if (int32_t rc = pass_error(err[0] | err[1])) return rc;
   for (int64_t q = 0; q < cnt; ++q) {
     const int64_t idx = S.n_hist - cnt + q;
     out[q] = ring[size_t(idx % P.hist_cap)];
@@ -521,6 +590,40 @@ int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj
   HIP_TRY(hipStreamSynchronize(S.stream), "hipStreamSynchronize");
   if (obj) *obj = sc[0];
   if (nviol) *nviol = int64_t(sc[1]);
+  return BDDMP_OK;
+}
+
+int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
+  const Plan &P = *S.plan;
+  if (mode != 0 && mode != 1) return set_error(BDDMP_INVALID_ARG, "launch mode must be 0 (wave launches) or 1 (dataflow)");
+  if (chunk < 0 || chunk > 4096) return set_error(BDDMP_INVALID_ARG, "chunk must be 0 (default) .. 4096");
+  if (mode == 1 && !P.pers_ok)
+    return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow launch");
+  if (mode == 1) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    for (int p = 0; p < 2; ++p) {
+      int per_cu = 0;
+      HIP_TRY(pass_blocks_per_cu(p ? kBwd : kFwd, P.n_general == 0, &per_cu), "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+      PassArgs &pa = S.pass[p];
+      pa.chunk = chunk ? chunk : 1;
+      pa.spin_limit = kPassSpinLimit;
+      if (const char *e = std::getenv("BDDMP_PASS_SPIN_LIMIT")) pa.spin_limit = uint32_t(std::strtoul(e, nullptr, 10));
+      const auto &qptr = p ? P.bqptr : P.fqptr;
+      int64_t n_chunks = 0;
+      for (size_t g = 0; g + 1 < qptr.size(); ++g) n_chunks += (int64_t(qptr[g + 1] - qptr[g]) + pa.chunk - 1) / pa.chunk;
+      S.pass_grid[p] = int(std::min<int64_t>(n_chunks, int64_t(std::max(per_cu, 1)) * std::max(ncu, 1)));
+    }
+  }
+  S.dataflow = mode == 1;
+  drop_graph(S);
+  return BDDMP_OK;
+}
+
+int32_t solver_get_launch(const Solver &S, int32_t *mode, int32_t *chunk) {
+  if (mode) *mode = S.dataflow ? 1 : 0;
+  if (chunk) *chunk = S.pass[0].chunk;
   return BDDMP_OK;
 }
 
@@ -628,7 +731,7 @@ int32_t solver_time_kernels(Solver &S, int32_t n, bddmp_kernel_times *out) {
   // backward pass
   const double pass_bytes = 20.0 * double(P.N) + 8.0 * double(P.I);
   const double turn_bytes =
-      P.fuse_turn ? 20.0 * double(P.fwd_waves.back().nodes) + 8.0 * double(P.fwd_waves.back().layers) : 0.0;
+      use_turn(S) ? 20.0 * double(P.fwd_waves.back().nodes) + 8.0 * double(P.fwd_waves.back().layers) : 0.0;
   r.fwd_bytes = (pass_bytes - turn_bytes) * n;
   r.bwd_bytes = (pass_bytes + turn_bytes) * n;
   *out = r;

@@ -1,0 +1,148 @@
+"""CPU emulation of the dataflow launch's protocol (no GPU).
+
+The plan groups independent instances; each group's tiles form a queue with a ticket counter that
+hands out chunks of consecutive queue tiles in order. A workgroup starts at queue b mod Q, takes
+chunks (drawing the next one while the current one runs), moves to the next queue when one runs
+dry and leaves after finding every queue dry. Before a tile runs, its workgroup waits for the flags
+of the tiles it depends on (flags carry the launch's generation); after the tile it publishes the
+tile's own flag. The last workgroup to leave resets the counters and advances the generation.
+
+The emulation interleaves the workgroups' steps at random, lets only a few of them be resident at
+once (the others start when one leaves, as a GPU dispatches them), and runs several launches back
+to back on the plan's real dependency lists and groups. It checks that every tile runs once per
+launch, after every tile it depends on, that no wait exhausts its bound, and that the planner's
+dependencies stay inside a group and point to smaller tiles; as controls, a dependency on a later
+tile or across groups (which the planner never emits) can block with few resident workgroups.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_00481_amd import binding as B
+from paper_2009_00481_amd import instances as I
+
+
+class Launches:
+    """Shared device state (counters, gone count, generation, flags) and one launch at a time."""
+
+    def __init__(self, dep_ptr, dep_list, tile_group, chunk):
+        self.ptr, self.lst, self.K = dep_ptr, dep_list, chunk
+        self.n = len(dep_ptr) - 1
+        self.Q = int(tile_group.max()) + 1 if self.n else 1
+        self.queues = [[t for t in range(self.n) if tile_group[t] == g] for g in range(self.Q)]
+        self.ticket = [0] * self.Q
+        self.gone = self.gen_word = 0
+        self.flags = [0] * max(self.n, 1)
+        self.error = False
+
+    def launch(self, grid, resident, rng, spin_limit=10_000):
+        done_at = {}
+        waiting = list(range(grid))      # not yet dispatched, in order
+        running = {}
+
+        def draw(q):
+            k = self.ticket[q]
+            self.ticket[q] += 1
+            return k
+
+        def program(w):
+            gen = self.gen_word + 1
+            q, tried = w % self.Q, 1
+            k = draw(q)
+            yield
+            while True:
+                while k * self.K >= len(self.queues[q]) and tried < self.Q:
+                    q, tried = (q + 1) % self.Q, tried + 1
+                    k = draw(q)
+                    yield
+                if k * self.K >= len(self.queues[q]):
+                    break
+                nxt = draw(q)            # drawn while the chunk runs
+                yield
+                for t in self.queues[q][k * self.K:(k + 1) * self.K]:
+                    for u in self.lst[self.ptr[t]:self.ptr[t + 1]]:
+                        spins = 0
+                        while self.flags[u] != gen:
+                            spins += 1
+                            if spins > spin_limit:
+                                self.error = True  # the kernel would go on with stale values
+                                return
+                            yield
+                    for u in self.lst[self.ptr[t]:self.ptr[t + 1]]:
+                        assert u in done_at, f"tile {t} ran before its dependency {u}"
+                    assert t not in done_at, f"tile {t} ran twice"
+                    done_at[t] = len(done_at)
+                    yield
+                    self.flags[t] = gen
+                    yield
+                k = nxt
+            gone = self.gone
+            self.gone += 1
+            if gone == grid - 1:
+                self.ticket, self.gone, self.gen_word = [0] * self.Q, 0, gen
+
+        while waiting or running:
+            while waiting and len(running) < resident:
+                w = waiting.pop(0)
+                running[w] = program(w)
+            w = rng.choice(list(running))
+            try:
+                next(running[w])
+            except StopIteration:
+                del running[w]
+            if self.error:
+                return done_at
+        return done_at
+
+
+def _plans():
+    return {
+        "cfg1": lambda: B.Plan(B.Problem.from_ilp(I.config(1))),
+        "rand": lambda: B.Plan(B.Problem.from_ilp(I.random_ilp(80, 60, kmax=9, cmax=3, seed=3))),
+        "batch": lambda: B.Plan([B.Problem.from_ilp(q) for q in
+                                 (I.tomography(6, seed=0), I.tracking(250, seed=1), I.config(1),
+                                  I.random_ilp(30, 20, seed=5), I.tomography(5, seed=8))]),
+    }
+
+
+@pytest.mark.parametrize("name", list(_plans()))
+@pytest.mark.parametrize("chunk", [1, 2, 5])
+def test_protocol_runs_every_tile_after_its_dependencies(name, chunk):
+    plan = _plans()[name]()
+    rng = np.random.default_rng(chunk)
+    for pass_ in (0, 1):
+        ptr, lst, grp = plan.tile_deps(pass_)
+        n = len(ptr) - 1
+        for t in range(n):
+            for q in range(ptr[t], ptr[t + 1]):
+                assert lst[q] < t and grp[lst[q]] == grp[t]
+        if name == "batch":
+            assert plan.stats.n_groups == 5 and set(grp.tolist()) == set(range(5))
+        st = Launches(ptr, lst, grp, chunk)
+        for k in range(4):
+            # any grid and any number of resident workgroups, down to one
+            grid = int(rng.integers(1, n + 2))
+            resident = int(rng.integers(1, min(grid, 6) + 1))
+            done = st.launch(grid, resident, rng)
+            assert not st.error, (name, pass_, k, grid, resident)
+            assert sorted(done) == list(range(n))
+            assert st.gen_word == k + 1 and st.ticket == [0] * st.Q and st.gone == 0
+
+
+def test_a_dependency_on_a_later_tile_can_block():
+    """Control: tile 0 waiting for tile 5 with one resident workgroup never sees it done."""
+    ptr = np.array([0, 1, 1, 1, 1, 1, 1])
+    lst = np.array([5])
+    st = Launches(ptr, lst, np.zeros(6, np.int32), 1)
+    st.launch(grid=6, resident=1, rng=np.random.default_rng(0), spin_limit=200)
+    assert st.error
+
+
+def test_a_dependency_across_groups_can_block():
+    """Control: tile 2 (group 1) waits for tile 1 (group 0), tile 0 waits for tile 2. Workgroup 0
+    takes tile 0 from queue 0 and waits; workgroup 1 takes tile 2 from queue 1 and waits for tile
+    1, which only queue 0's next draw would take: with those two resident, nothing moves."""
+    ptr = np.array([0, 1, 1, 2, 2])
+    lst = np.array([2, 1])
+    st = Launches(ptr, lst, np.array([0, 0, 1, 1]), 1)
+    st.launch(grid=2, resident=2, rng=np.random.default_rng(2), spin_limit=300)
+    assert st.error

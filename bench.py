@@ -76,6 +76,22 @@ def committed_traffic(workload: str):
     return None
 
 
+def roofline_of(kt, traffic_rec):
+    """The dominant wave kernel class (the pass direction with the larger summed time) priced against
+    MI355X HBM peak: model bytes per launch over the average launch time (HIP events around whole
+    passes on the solver's stream); traffic from the committed counter summary, or None."""
+    if kt["fwd_ms"] >= kt["bwd_ms"]:
+        kname, kms, kb, kl = "wave_kernel<fwd,update>", kt["fwd_ms"], kt["fwd_bytes"], kt["fwd_launches"]
+    else:
+        kname, kms, kb, kl = "wave_kernel<bwd,update>", kt["bwd_ms"], kt["bwd_bytes"], kt["bwd_launches"]
+    achieved = (kb / kl) / ((kms / kl) * 1e-3) / 1e9
+    traffic = None if traffic_rec is None else traffic_rec["fwd" if "fwd" in kname else "bwd"]
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+            "kernel": kname, "bytes_per_launch": kb / kl, "avg_launch_us": kms / kl * 1e3,
+            "both_passes_gbs": round((kt["fwd_bytes"] + kt["bwd_bytes"]) / ((kt["fwd_ms"] + kt["bwd_ms"]) * 1e-3) / 1e9, 1)}
+
+
 def oracle_bounds(workload: str, T: int):
     """The fp64 oracle's bounds LB_0..LB_T on the workload (written by
     tests/golden/make_oracle_bounds.py), or None when they are not stored for T iterations."""
@@ -125,6 +141,18 @@ def batched_vs_plain(args, B, I, torch):
     bs.iterate(T)
     torch.cuda.synchronize()
     batched_ms = (time.perf_counter() - t0) * 1e3 / T
+    # the dominant wave kernel of the batched schedule against HBM peak (events around whole
+    # passes, as for the main workload), and the dataflow launch of the same passes
+    kt = bs.time_kernels(3)
+    roofline = roofline_of(kt, committed_traffic(f"batch{n}"))
+    bs.set_launch(1, 1)
+    bs.iterate(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.iterate(T)
+    torch.cuda.synchronize()
+    dataflow_ms = (time.perf_counter() - t0) * 1e3 / T
+    bs.set_launch(0, 0)
     # bitwise check on a sample: the same iterations from the start, batched and plain
     Tc = 5
     bs.reset()
@@ -136,7 +164,7 @@ def batched_vs_plain(args, B, I, torch):
     torch.cuda.empty_cache()
     plain_ms, plain_plan_s, equal = 0.0, 0.0, 0
     kp = args.batch_plain_iters
-    for k, pr in enumerate(probs):
+    for k, pr in enumerate(probs if kp > 0 else []):
         tp = time.perf_counter()
         p = B.Plan(pr)
         plain_plan_s += time.perf_counter() - tp
@@ -161,10 +189,12 @@ def batched_vs_plain(args, B, I, torch):
             "instances": n, "n_nodes": int(st.n_nodes), "n_incidences": int(st.n_incidences),
             "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
             "batched_ms_per_iter": batched_ms, "plain_ms_per_iter": plain_ms,
-            "speedup": plain_ms / batched_ms,
+            "speedup": plain_ms / batched_ms if kp > 0 else None,
             "batched_arc_updates_per_s": arcs / (batched_ms * 1e-3),
-            "plain_arc_updates_per_s": arcs / (plain_ms * 1e-3),
+            "plain_arc_updates_per_s": arcs / (plain_ms * 1e-3) if kp > 0 else None,
             "batched_model_gbps": model / (batched_ms * 1e-3) / 1e9,
+            "roofline": roofline,
+            "dataflow_launch_ms_per_iter": dataflow_ms,
             "timed_iters": {"batched": T, "plain_per_instance": kp},
             "bitwise_equal_instances": f"{equal}/{len(sample)} sampled after {Tc} iterations",
             "host_build_s": {"generate": gen_s, "batched_plan": plan_s, "plain_plans": plain_plan_s},
@@ -337,7 +367,8 @@ def main():
                     help="run only this comparison and print its object (profiling)")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=20)
-    ap.add_argument("--batch-plain-iters", type=int, default=3)
+    ap.add_argument("--batch-plain-iters", type=int, default=3,
+                    help="timed iterations per instance of the one-by-one comparison (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -430,29 +461,31 @@ def main():
     iter_ms = kt["iter_ms"]
     gbps_iter = iter_bytes / (iter_ms * 1e-3) / 1e9 if iter_ms > 0 else None
 
-    # dominant kernel: the wave kernel class with the larger summed time
-    if kt["fwd_ms"] >= kt["bwd_ms"]:
-        kname, kms, kb, kl = "wave_kernel<fwd,update>", kt["fwd_ms"], kt["fwd_bytes"], kt["fwd_launches"]
-    else:
-        kname, kms, kb, kl = "wave_kernel<bwd,update>", kt["bwd_ms"], kt["bwd_bytes"], kt["bwd_launches"]
-    achieved = (kb / kl) / ((kms / kl) * 1e-3) / 1e9
-    tr = committed_traffic(args.workload)
-    traffic = None if tr is None else tr["fwd" if "fwd" in kname else "bwd"]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
-                "kernel": kname,
-                "bytes_per_launch": kb / kl, "avg_launch_us": kms / kl * 1e3,
-                "both_passes_gbs": round((kt["fwd_bytes"] + kt["bwd_bytes"]) / ((kt["fwd_ms"] + kt["bwd_ms"]) * 1e-3) / 1e9, 1)}
+    roofline = roofline_of(kt, committed_traffic(args.workload))
 
     # time to bound: first t with LB_t >= LB* - 1e-4 max(|LB*|, 1). LB* is the fp64 oracle's LB_T on
-    # the same instance when it is stored for T iterations, else this run's own LB_T.
+    # the same instance when it is stored for T iterations, else this run's own LB_T. Measured with
+    # HIP events recorded on the solver's stream after every iteration of a separate run from the
+    # reset (no host synchronisation in the loop); the reset itself is not counted.
     lb_self = float(hist[-1])
     ref = oracle_bounds(args.workload, T)
     lb_star = float(ref[-1]) if ref is not None else lb_self
     thr = lb_star - 1e-4 * max(abs(lb_star), 1.0)
     hit = hist >= thr
     t_hit = int(np.argmax(hit)) if hit.any() else None
-    ttb_ms = t_hit * iter_ms if t_hit is not None else None
+    ttb_ms = None
+    if t_hit is not None:
+        stream = torch.cuda.current_stream()
+        B.bddmp_solver_reset(s.h)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(t_hit + 1)]
+        ev[0].record(stream)
+        for t in range(1, t_hit + 1):
+            B.bddmp_solver_iterate(s.h, 1)
+            ev[t].record(stream)
+        torch.cuda.synchronize()
+        ttb_ms = ev[0].elapsed_time(ev[t_hit])
+        h_ev = s.lb_history(t_hit + 1)
+        assert np.array_equal(h_ev, hist[:t_hit + 1]), "per-iteration run differs from the step's trajectory"
     vs_oracle = None
     if ref is not None:
         gap = (hist - ref) / np.maximum(np.abs(ref), 1.0)
@@ -524,6 +557,7 @@ def main():
                    "bound_dtype": "f64"},
         "hbm_gbps_per_iter": gbps_iter, "iter_ms": iter_ms, "model_bytes_per_iter": iter_bytes,
         "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit,
+        "time_to_bound_from_iter_ms": None if t_hit is None else t_hit * iter_ms,
         "lb_star_source": "oracle fp64 LB_T" if ref is not None else "this run's LB_T",
         "bound_vs_oracle": vs_oracle, "lb_final": lb_self, "lb_0": float(hist[0]),
         "primal_obj": obj, "primal_violated_rows": int(nviol), "primal_search": search,

@@ -8,7 +8,11 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bddmp_oracle.c")
-TARGETS = {"f64": os.path.join(HERE, "liboracle_f64.so"), "f32": os.path.join(HERE, "liboracle_f32.so")}
+# BDDMP_SANITIZE=1: the oracle built with AddressSanitizer and UBSan (run with libasan preloaded)
+SANITIZE = os.environ.get("BDDMP_SANITIZE") == "1"
+_SUFFIX = "_san" if SANITIZE else ""
+TARGETS = {"f64": os.path.join(HERE, f"liboracle_f64{_SUFFIX}.so"), "f32": os.path.join(HERE, f"liboracle_f32{_SUFFIX}.so")}
+SANITIZE_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 
 def build(force: bool = True) -> dict:
@@ -17,6 +21,8 @@ def build(force: bool = True) -> dict:
             continue
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
                "-Wall", "-Wextra", "-Wno-unused-parameter", SRC, "-o", out + ".tmp", "-lm"]
+        if SANITIZE:
+            cmd[1:1] = SANITIZE_FLAGS
         if prec == "f32":
             cmd.insert(1, "-DORC_REAL_FLOAT")
         subprocess.run(cmd, check=True)

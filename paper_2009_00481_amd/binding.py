@@ -17,6 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbddmp.so")
+# BDDMP_HOST_ONLY_LIB names the host-only sanitizer test build (build.build_host_only): the host
+# calls are the library's own, every device call fails with DEVICE; no HIP runtime is loaded
+HOST_ONLY_LIB = os.environ.get("BDDMP_HOST_ONLY_LIB")
 
 BDDMP_OK = 0
 STATUS = {-1: "INVALID_ARG", -2: "ROW_INFEASIBLE", -3: "BDD_TOO_LARGE", -4: "NOT_INTEGER", -5: "CONFLICT",
@@ -116,15 +119,17 @@ def lib():
     """Load libbddmp.so (built in-tree by ``paper_2009_00481_amd/build.py``); raise if missing."""
     global _lib
     if _lib is None:
-        # torch first: its HIP runtime carries the soname the library links against, so the
-        # library binds to that same runtime (one runtime, one device context, shared streams).
-        # Loaded the other way round, the process would hold two HIP runtimes.
-        import torch  # noqa: F401
+        path = HOST_ONLY_LIB or LIB_PATH
+        if not HOST_ONLY_LIB:
+            # torch first: its HIP runtime carries the soname the library links against, so the
+            # library binds to that same runtime (one runtime, one device context, shared streams).
+            # Loaded the other way round, the process would hold two HIP runtimes.
+            import torch  # noqa: F401
 
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run paper_2009_00481_amd/build.py "
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run paper_2009_00481_amd/build.py "
                               "(the HIP library has no fallback)")
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
             fn.restype = res

@@ -30,6 +30,30 @@ def _run(cmd):
     return r
 
 
+HOST_ONLY_SOURCES = ["primal.cpp", "builder.cpp", "plan.cpp", "capi.cpp", "solver_host_only.cpp"]
+HOST_ONLY_LIB = os.path.join(HERE, "libbddmp_host_san.so")
+# the host-only test build under the CPU sanitizers (run with libasan preloaded; see README)
+SANITIZE_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build_host_only(verbose: bool = False) -> str:
+    """The host half of the library (builder, planner, primal search, C-ABI checks) with the solver
+    calls stubbed to fail with BDDMP_DEVICE, built with AddressSanitizer and UBSan for the CPU tests."""
+    objs = []
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", INCLUDE, "-I", CSRC]
+    for src in HOST_ONLY_SOURCES:
+        o = os.path.join(OBJ, "san_" + src + ".o")
+        _run(["g++", *HOST_FLAGS, *SANITIZE_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
+    tmp = HOST_ONLY_LIB + ".tmp"
+    _run(["g++", "-shared", "-fPIC", *SANITIZE_FLAGS, *objs, "-o", tmp])
+    os.replace(tmp, HOST_ONLY_LIB)
+    if verbose:
+        print("built", HOST_ONLY_LIB)
+    return HOST_ONLY_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     objs = []
@@ -51,4 +75,7 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--host-only-sanitized" in sys.argv:
+        build_host_only(verbose=True)
+    else:
+        build(verbose=True)

@@ -211,10 +211,13 @@ def test_smooth_argument_errors():
 
 
 def test_full_size_differentiable_workload():
-    """The 128x128, 4-label Potts workload at full size, as the benchmark runs it (50 iterations, one
-    checkpoint per iteration): the first smoothed bounds against the fp64 oracle, the whole trace
-    non-decreasing, and a finite gradient (its values are checked against the oracle's adjoint and
-    finite differences on the smaller instances above)."""
+    """The 128x128, 4-label Potts workload at full size, as the benchmark runs it (alpha = 0.1, 50
+    iterations, one checkpoint per iteration): the first smoothed bounds against the fp64 oracle,
+    the whole trace non-decreasing, the final bound and the gradient d LB_alpha / d c at the
+    oracle's stored sample of 1,000 coordinates (its fp64 adjoint, tests/golden/
+    make_oracle_samples.py) at the gradient bar, relative to max(1, max |g|) over all coordinates."""
+    import os
+
     import torch
 
     ilp = I.config(5)
@@ -229,6 +232,12 @@ def test_full_size_differentiable_workload():
     assert np.all(np.diff(h) >= -1e-6 * np.maximum(np.abs(h[1:]), 1.0))
     g = r["grad"]
     assert np.all(np.isfinite(g))
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "potts128x128_L4_grad.npz"))
+    assert float(ref["alpha"]) == alpha and int(ref["iterations"]) == T
+    assert h[-1] == pytest.approx(float(ref["lb"]), rel=REL, abs=REL)
+    err = np.abs(g[ref["idx"]] - ref["grad"]).max() / max(1.0, float(ref["grad_abs_max"]))
+    print(f"  sampled gradient max rel err {err:.3g}", flush=True)
+    assert err <= _grad_tol(T, r["plan"].stats.max_rows_per_var)
     torch.cuda.synchronize()
 
 

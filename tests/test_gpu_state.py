@@ -1,5 +1,7 @@
 """GPU behaviour beyond element parity: determinism, checkpoint/resume, edge cases, argument errors,
 the timing entry point, and the full-size MRF workload (sampled against the oracle)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -214,6 +216,18 @@ def test_full_size_mrf_workload():
     assert hist[-1] > hist[0]
     assert resid <= 1e-4 * float(np.abs(ilp.cost).max())
     assert any_lb <= lb + 1e-9
+    # the end state element by element: multipliers and fresh min-marginals after the 500
+    # iterations at the oracle's stored sample of 100,000 incidences (tests/golden/
+    # make_oracle_samples.py), at the per-incidence bar
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "potts256x256_L8.npz"))
+    assert int(ref["iterations"]) == 500
+    idx = ref["idx"]
+    lam = s.get_lambda().cpu().numpy().astype(np.float64)
+    m0, m1 = s.min_marginals()
+    torch.cuda.synchronize()
+    assert_incidence_close(lam[idx], ref["lam"], ref["scale"], what="lambda after 500 iterations (sampled)")
+    assert_incidence_close(m0.cpu().numpy().astype(np.float64)[idx], ref["m0"], ref["scale"], what="m0 after 500 (sampled)")
+    assert_incidence_close(m1.cpu().numpy().astype(np.float64)[idx], ref["m1"], ref["scale"], what="m1 after 500 (sampled)")
 
 
 def test_iterate_until_stop_rule():

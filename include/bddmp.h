@@ -239,6 +239,19 @@ int32_t bddmp_plan_export_structure(const bddmp_plan *plan, int32_t *level_width
 int32_t bddmp_plan_export_tile_deps(const bddmp_plan *plan, int32_t pass, int32_t *dep_ptr, int32_t *dep_list,
                                     int32_t *tile_group);
 
+/*
+ * Two-branch split of each wave of one pass (launch mode 2 of bddmp_solver_set_launch), for
+ * inspection and host-side checks: pass 0 forward, 1 backward; W = waves_fwd or waves_bwd of
+ * bddmp_stats. tile_begin host [W + 1]: wave w holds the pass's tiles [tile_begin[w],
+ * tile_begin[w+1]) (the numbering of bddmp_plan_export_tile_deps); mid host [W]: part A of wave w
+ * is [tile_begin[w], mid[w]), part B the rest; b_wait host [W]: part B of wave w runs after part A
+ * of wave b_wait[w] (-1: it reads no A tile). Every tile of an A part depends only on A tiles of
+ * earlier waves, every tile of a B part on B tiles of earlier waves or A tiles of waves up to
+ * b_wait. Any pointer may be NULL. INVALID_ARG for a plan without tile dependency lists.
+ */
+int32_t bddmp_plan_export_wave_split(const bddmp_plan *plan, int32_t pass, int32_t *tile_begin, int32_t *mid,
+                                     int32_t *b_wait);
+
 /* Forward and backward wave of every variable (1-based, 0 for variables in no row); host [n_vars]. */
 int32_t bddmp_plan_export_waves(const bddmp_plan *plan, int32_t *wave_fwd, int32_t *wave_bwd);
 
@@ -415,7 +428,14 @@ int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
  * as with wave launches (the same operations in the same order per layer). Each wait for another
  * tile is bounded; a wait that exceeds its bound (about a second; not expected while the GPU runs
  * only this work) makes the next lower_bound / lb_history return DEVICE until bddmp_solver_reset.
- * INVALID_ARG for mode 1 on a plan without dataflow support. get: either pointer may be NULL.
+ * mode 2 (two-branch wave launches; plans with bddmp_stats.dataflow = 1): every wave is split in
+ * two parts (bddmp_plan_export_wave_split). The A parts are launched in order on the solver's
+ * stream and never wait for a B part; the B parts are launched in order on a second stream (created
+ * by this call, default priority), each after the A part of the latest wave it reads from. A pass
+ * ends when both streams are done. Captured as a graph, the two chains run side by side, so one
+ * wave's last workgroups overlap the next wave's first ones. The turnaround and wrap-around fusions
+ * are not used; results are bitwise those of mode 0. chunk is ignored by modes 0 and 2.
+ * INVALID_ARG for mode 1 or 2 on a plan without dataflow support. get: either pointer may be NULL.
  * For tests of that failure path, the environment variable BDDMP_PASS_SPIN_LIMIT (read by this
  * call) replaces the bound: the polls of one wait before it gives up.
  */

@@ -82,6 +82,7 @@ SIGNATURES = {
     "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_plan_export_waves": (_I32, [_P, _P, _P]),
     "bddmp_plan_export_tile_deps": (_I32, [_P, _I32, _P, _P, _P]),
+    "bddmp_plan_export_wave_split": (_I32, [_P, _I32, _P, _P, _P]),
     "bddmp_solver_bind": (_I32, [_P, _P, C.c_size_t, _P, C.POINTER(_P)]),
     "bddmp_solver_reset": (_I32, [_P]),
     "bddmp_solver_iterate": (_I32, [_P, _I32]),
@@ -283,6 +284,14 @@ def bddmp_plan_export_tile_deps(plan, pass_: int, n_tiles: int, n_deps: int):
     grp = np.zeros(max(n_tiles, 1), np.int32)
     _check(lib().bddmp_plan_export_tile_deps(plan, int(pass_), _ptr(ptr), _ptr(lst), _ptr(grp)))
     return ptr, lst[:n_deps], grp[:n_tiles]
+
+
+def bddmp_plan_export_wave_split(plan, pass_: int, n_waves: int):
+    begin = np.zeros(n_waves + 1, np.int32)
+    mid = np.zeros(max(n_waves, 1), np.int32)
+    bw = np.zeros(max(n_waves, 1), np.int32)
+    _check(lib().bddmp_plan_export_wave_split(plan, int(pass_), _ptr(begin), _ptr(mid), _ptr(bw)))
+    return begin, mid[:n_waves], bw[:n_waves]
 
 
 def bddmp_solver_bind(plan, arena, nbytes: int, stream):
@@ -499,6 +508,11 @@ class Plan:
         st = self.stats
         n = int(st.fwd_tiles if pass_ == 0 else st.bwd_tiles)
         return bddmp_plan_export_tile_deps(self.h, pass_, n, int(st.tile_deps_fwd if pass_ == 0 else st.tile_deps_bwd))
+
+    def wave_split(self, pass_: int):
+        """(tile_begin [W + 1], mid [W], b_wait [W]) of the two-branch launch of pass 0 or 1."""
+        st = self.stats
+        return bddmp_plan_export_wave_split(self.h, pass_, int(st.waves_fwd if pass_ == 0 else st.waves_bwd))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

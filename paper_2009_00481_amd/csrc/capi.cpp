@@ -331,6 +331,23 @@ int32_t bddmp_plan_export_tile_deps(const bddmp_plan *h, int32_t pass, int32_t *
   return BDDMP_OK;
 }
 
+int32_t bddmp_plan_export_wave_split(const bddmp_plan *h, int32_t pass, int32_t *tile_begin, int32_t *mid,
+                                     int32_t *b_wait) {
+  if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
+  if (pass != 0 && pass != 1) return set_error(BDDMP_INVALID_ARG, "pass must be 0 (forward) or 1 (backward)");
+  const bddmp::Plan &P = h->plan;
+  if (!P.pers_ok) return set_error(BDDMP_INVALID_ARG, "the plan has no tile dependency lists");
+  const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+  const auto &split = pass ? P.bsplit : P.fsplit;
+  for (size_t w = 0; w < waves.size(); ++w) {
+    if (tile_begin) tile_begin[w] = waves[w].tile_begin;
+    if (mid) mid[w] = split[w].mid;
+    if (b_wait) b_wait[w] = split[w].b_wait;
+  }
+  if (tile_begin) tile_begin[waves.size()] = waves.empty() ? 0 : waves.back().tile_end;
+  return BDDMP_OK;
+}
+
 int32_t bddmp_plan_export_waves(const bddmp_plan *h, int32_t *wave_fwd, int32_t *wave_bwd) {
   if (!h) return set_error(BDDMP_INVALID_ARG, "null plan");
   const bddmp::Plan &P = h->plan;

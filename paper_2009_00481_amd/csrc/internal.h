@@ -203,6 +203,15 @@ struct Plan {
   int32_t n_groups = 1;
   std::vector<int32_t> var_group;
   std::vector<int32_t> fqptr, fqtile, bqptr, bqtile;
+  // Two-branch wave launches (plans with dependency lists): each wave's tiles split at mid into a
+  // part A [tile_begin, mid) and a part B [mid, tile_end). Every tile of an A part depends only on
+  // tiles of earlier A parts, so the A parts run in order on one stream without waiting for B; the
+  // B parts run in order on a second stream, part B of wave w after part A of wave b_wait (-1: no
+  // A tile). A part is at most half of its wave (rounded up).
+  struct WaveSplit {
+    int32_t mid, b_wait;
+  };
+  std::vector<WaveSplit> fsplit, bsplit;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes
   uint32_t gsel = kDefaultGsel;

@@ -350,6 +350,27 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
           for (int32_t q = ptr[size_t(t)]; q < ptr[size_t(t) + 1]; ++q)
             if (tq[size_t(lst[size_t(q)])] != tq[size_t(t)]) return "dependency across groups";
         }
+      // two-branch split: an A tile depends on A tiles of earlier waves only; a B tile on B tiles of
+      // earlier waves or A tiles of waves up to its wave's b_wait
+      const auto &split = pass ? P.bsplit : P.fsplit;
+      if (split.size() != waves.size()) return "wave split arrays";
+      std::vector<int32_t> wave_of(nt, -1);
+      for (size_t w = 0; w < waves.size(); ++w) {
+        const WaveRange &wr = waves[w];
+        const Plan::WaveSplit &s = split[w];
+        if (s.mid < wr.tile_begin || s.mid > wr.tile_end || 2 * (s.mid - wr.tile_begin) > wr.tile_end - wr.tile_begin + 1 ||
+            s.b_wait < -1 || s.b_wait >= int32_t(w))
+          return "wave split";
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+          wave_of[size_t(t)] = int32_t(w);
+          for (int32_t q = ptr[size_t(t)]; q < ptr[size_t(t) + 1]; ++q) {
+            const int32_t u = lst[size_t(q)], wu = wave_of[size_t(u)];
+            if (wu < 0 || wu >= int32_t(w)) return "dependency not in an earlier wave";
+            const bool u_in_a = u < split[size_t(wu)].mid;
+            if (t < s.mid ? !u_in_a : (u_in_a && wu > s.b_wait)) return "wave split dependency";
+          }
+        }
+      }
     }
   }
   for (int32_t j = 0; j < P.m; ++j)
@@ -1031,6 +1052,8 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   P.bdep_list.clear();
   P.ftinfo.clear();
   P.btinfo.clear();
+  P.fsplit.clear();
+  P.bsplit.clear();
   if (P.pers_ok) {
     std::vector<int32_t> tile_of(In0, -1), d;
     for (int pass = 0; pass < 2; ++pass) {
@@ -1105,6 +1128,28 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
         rec[8 * t + 2] = int32_t(info[t] | (uint32_t(nd) << 8));
         rec[8 * t + 3] = ptr[t];
         for (int32_t q = 0; q < std::min(nd, 4); ++q) rec[8 * t + 4 + q] = lst[size_t(ptr[t] + q)];
+      }
+      // two-branch split of each wave: the longest prefix whose dependencies all lie in earlier
+      // prefixes, cut at half the wave; the rest waits for the latest prefix it reads from
+      auto &split = pass ? P.bsplit : P.fsplit;
+      split.assign(waves.size(), Plan::WaveSplit{0, -1});
+      std::vector<int32_t> wave_of(nt, 0);
+      for (size_t w = 0; w < waves.size(); ++w) {
+        const WaveRange &wr = waves[w];
+        for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) wave_of[size_t(t)] = int32_t(w);
+        const int32_t cap = wr.tile_begin + (wr.tile_end - wr.tile_begin + 1) / 2;
+        int32_t mid = wr.tile_begin;
+        auto in_a = [&](int32_t u) { return u < split[size_t(wave_of[size_t(u)])].mid; };
+        for (; mid < cap; ++mid) {
+          bool ok = true;
+          for (int32_t q = ptr[size_t(mid)]; ok && q < ptr[size_t(mid) + 1]; ++q) ok = in_a(lst[size_t(q)]);
+          if (!ok) break;
+        }
+        int32_t b_wait = -1;
+        for (int32_t t = mid; t < wr.tile_end; ++t)
+          for (int32_t q = ptr[size_t(t)]; q < ptr[size_t(t) + 1]; ++q)
+            if (in_a(lst[size_t(q)])) b_wait = std::max(b_wait, wave_of[size_t(lst[size_t(q)])]);
+        split[w] = Plan::WaveSplit{mid, b_wait};
       }
     }
   }

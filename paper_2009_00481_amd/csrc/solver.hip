@@ -44,10 +44,18 @@ struct Solver {
   bool dataflow = false;
   PassArgs pass[2]{};
   int pass_grid[2] = {0, 0};
+  // two-branch wave launches: on or off, the second stream of eager launches and of captures, and
+  // the events ordering the branches (per pass: fork, join, then one per wave after its A part)
+  bool pipe = false;
+  hipStream_t side = nullptr, cap_side = nullptr;
+  std::vector<hipEvent_t> pipe_ev;
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gexec_wrap) (void)hipGraphExecDestroy(gexec_wrap);
     if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    if (cap_side) (void)hipStreamDestroy(cap_side);
+    for (hipEvent_t e : pipe_ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -77,9 +85,10 @@ int32_t pass_error(uint32_t err) {
                                  "last reset are invalid");
 }
 
-// the turnaround and wrap-around launches fuse wave launches; the dataflow launch has none
-bool use_turn(const Solver &S) { return S.plan->fuse_turn && !S.dataflow; }
-bool use_wrap(const Solver &S) { return S.plan->fuse_wrap && !S.dataflow; }
+// the turnaround and wrap-around launches fuse wave launches; the dataflow and two-branch launches
+// have none
+bool use_turn(const Solver &S) { return S.plan->fuse_turn && !S.dataflow && !S.pipe; }
+bool use_wrap(const Solver &S) { return S.plan->fuse_wrap && !S.dataflow && !S.pipe; }
 
 // NONFINITE unless every value of the device arrays (float or double, n each) is finite; checked on
 // the device, then the stream is synchronised to read the result.
@@ -125,6 +134,38 @@ struct Timer {
   }
 };
 
+// Two-branch launch of an update pass: the A part of every wave on st, the B parts on the second
+// stream (the capture's own while st is captured), forked from st at the start and joined back at
+// the end; part B of wave w waits for the event recorded after part A of wave b_wait.
+int32_t pipe_pass(Solver &S, int dir, hipStream_t st) {
+  const Plan &P = *S.plan;
+  const int p = dir == kFwd ? 0 : 1;
+  const auto &waves = p ? P.bwd_waves : P.fwd_waves;
+  const auto &split = p ? P.bsplit : P.fsplit;
+  hipStream_t side = st == S.cap ? S.cap_side : S.side;
+  hipEvent_t *ev = S.pipe_ev.data() + (p ? 2 + P.fwd_waves.size() : 0);
+  HIP_TRY(hipEventRecord(ev[0], st), "hipEventRecord");
+  HIP_TRY(hipStreamWaitEvent(side, ev[0], 0), "hipStreamWaitEvent");
+  for (size_t w = 0; w < waves.size(); ++w) {
+    const WaveRange &wr = waves[w];
+    const int32_t mid = split[w].mid;
+    const bool list = dir == kBwd && wr.list;
+    if (mid > wr.tile_begin)
+      if (int32_t rc = launched(launch_wave(dir, kUpdate, wr.narrow_only, list, mid - wr.tile_begin, wr.tile_begin, S.D, st),
+                                "wave kernel (part A)"))
+        return rc;
+    HIP_TRY(hipEventRecord(ev[2 + w], st), "hipEventRecord");
+    if (split[w].b_wait >= 0) HIP_TRY(hipStreamWaitEvent(side, ev[2 + split[w].b_wait], 0), "hipStreamWaitEvent");
+    if (wr.tile_end > mid)
+      if (int32_t rc = launched(launch_wave(dir, kUpdate, wr.narrow_only, list, wr.tile_end - mid, mid, S.D, side),
+                                "wave kernel (part B)"))
+        return rc;
+  }
+  HIP_TRY(hipEventRecord(ev[1], side), "hipEventRecord");
+  HIP_TRY(hipStreamWaitEvent(st, ev[1], 0), "hipStreamWaitEvent");
+  return BDDMP_OK;
+}
+
 // One pass: every wave in order, one launch per wave (plus one for the wave's big tiles if any).
 // turn (plans with fuse_turn, update mode): the forward pass stops before its last wave and the
 // backward pass's first launch runs that wave's forward update before its own (kTurn).
@@ -144,6 +185,14 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
     if (int32_t rc = launched(launch_pass(dir, P.n_general == 0, S.pass_grid[p], S.D, S.pass[p], st), "pass kernel"))
       return rc;
     return tm.stop(st, S.pass[p].n_tiles > 0 ? 1 : 0);
+  }
+  if (S.pipe && mode == kUpdate) {
+    if (int32_t rc = pipe_pass(S, dir, st)) return rc;
+    const auto &split = dir == kFwd ? P.fsplit : P.bsplit;
+    int parts = 0;
+    for (size_t w = 0; w < waves.size(); ++w)
+      parts += int(split[w].mid > waves[w].tile_begin) + int(waves[w].tile_end > split[w].mid);
+    return tm.stop(st, parts);
   }
   for (size_t w = w0; w < nw; ++w) {
     const WaveRange &wr = waves[w];
@@ -595,10 +644,21 @@ int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj
 
 int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
   const Plan &P = *S.plan;
-  if (mode != 0 && mode != 1) return set_error(BDDMP_INVALID_ARG, "launch mode must be 0 (wave launches) or 1 (dataflow)");
+  if (mode < 0 || mode > 2)
+    return set_error(BDDMP_INVALID_ARG, "launch mode must be 0 (wave launches), 1 (dataflow) or 2 (two-branch waves)");
   if (chunk < 0 || chunk > 4096) return set_error(BDDMP_INVALID_ARG, "chunk must be 0 (default) .. 4096");
-  if (mode == 1 && !P.pers_ok)
-    return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow launch");
+  if (mode != 0 && !P.pers_ok)
+    return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow or two-branch launch");
+  if (mode == 2) {
+    if (!S.side) HIP_TRY(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    if (!S.cap_side) HIP_TRY(hipStreamCreateWithFlags(&S.cap_side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    const size_t n_ev = 4 + P.fwd_waves.size() + P.bwd_waves.size();
+    while (S.pipe_ev.size() < n_ev) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+      S.pipe_ev.push_back(e);
+    }
+  }
   if (mode == 1) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
@@ -617,12 +677,13 @@ int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
     }
   }
   S.dataflow = mode == 1;
+  S.pipe = mode == 2;
   drop_graph(S);
   return BDDMP_OK;
 }
 
 int32_t solver_get_launch(const Solver &S, int32_t *mode, int32_t *chunk) {
-  if (mode) *mode = S.dataflow ? 1 : 0;
+  if (mode) *mode = S.dataflow ? 1 : (S.pipe ? 2 : 0);
   if (chunk) *chunk = S.pass[0].chunk;
   return BDDMP_OK;
 }

@@ -146,3 +146,81 @@ def test_a_dependency_across_groups_can_block():
     st = Launches(ptr, lst, np.array([0, 0, 1, 1]), 1)
     st.launch(grid=2, resident=2, rng=np.random.default_rng(2), spin_limit=300)
     assert st.error
+
+
+def _two_branch_run(ptr, lst, beg, mid, bw, rng):
+    """Runs the two chains of the two-branch launch in a random interleaving: chain A takes the A
+    parts in wave order without waiting, chain B takes part B of wave w once chain A has finished
+    wave bw[w]. Returns the order in which tiles finished."""
+    W = len(mid)
+    done_at, a_done = {}, -1
+    a_w = b_w = 0
+    while a_w < W or b_w < W:
+        can_a = a_w < W
+        can_b = b_w < W and bw[b_w] <= a_done
+        assert can_a or can_b, "the two chains wait for each other"
+        if can_a and (not can_b or rng.random() < 0.5):
+            for t in range(beg[a_w], mid[a_w]):
+                for u in lst[ptr[t]:ptr[t + 1]]:
+                    assert u in done_at, f"A tile {t} ran before {u}"
+            for t in range(beg[a_w], mid[a_w]):
+                done_at[t] = len(done_at)
+            a_done, a_w = a_w, a_w + 1
+        else:
+            for t in range(mid[b_w], beg[b_w + 1]):
+                for u in lst[ptr[t]:ptr[t + 1]]:
+                    assert u in done_at, f"B tile {t} ran before {u}"
+            for t in range(mid[b_w], beg[b_w + 1]):
+                done_at[t] = len(done_at)
+            b_w += 1
+    return done_at
+
+
+@pytest.mark.parametrize("name", list(_plans()))
+def test_two_branch_split_respects_every_dependency(name):
+    """The planner's split of each wave (bddmp_plan_export_wave_split) against its own dependency
+    lists: an A part reads only A tiles of earlier waves, a B part only B tiles of earlier waves or
+    A tiles up to its wave's b_wait (the latest such wave exactly), A is the longest such prefix up
+    to half the wave, and random interleavings of the two chains run every tile after its
+    dependencies."""
+    plan = _plans()[name]()
+    rng = np.random.default_rng(11)
+    for pass_ in (0, 1):
+        ptr, lst, _ = plan.tile_deps(pass_)
+        beg, mid, bw = plan.wave_split(pass_)
+        W = len(mid)
+        assert beg[0] == 0 and beg[-1] == len(ptr) - 1 and np.all(np.diff(beg) > 0)
+        wave = np.repeat(np.arange(W), np.diff(beg))
+        in_a = np.arange(len(ptr) - 1) < mid[wave]
+        for w in range(W):
+            n = beg[w + 1] - beg[w]
+            assert beg[w] <= mid[w] <= beg[w + 1] and 2 * (mid[w] - beg[w]) <= n + 1
+            latest = -1
+            for t in range(beg[w], beg[w + 1]):
+                d = lst[ptr[t]:ptr[t + 1]]
+                assert np.all(wave[d] < w)
+                if t < mid[w]:
+                    assert np.all(in_a[d])
+                else:
+                    if np.any(in_a[d]):
+                        latest = max(latest, int(wave[d][in_a[d]].max()))
+            assert bw[w] == latest, (pass_, w)
+            # the prefix stops at the cap or at the first tile reading a B tile
+            if mid[w] < beg[w] + (n + 1) // 2:
+                d = lst[ptr[mid[w]]:ptr[mid[w] + 1]]
+                assert not np.all(in_a[d])
+        for _ in range(5):
+            done = _two_branch_run(ptr, lst, beg, mid, bw, rng)
+            assert sorted(done) == list(range(len(ptr) - 1))
+
+
+def test_two_branch_split_is_balanced_on_a_grid_mrf():
+    """On the 128x128, 4-label Potts workload every wave's dependencies stay near the same relative
+    position, so the A parts hold close to half of each pass's tiles and each B part waits only for
+    the previous wave's A part."""
+    plan = B.Plan(B.Problem.from_ilp(I.config(5)))
+    for pass_ in (0, 1):
+        beg, mid, bw = plan.wave_split(pass_)
+        a = (mid - beg[:-1]).sum() / (beg[-1] - beg[0])
+        assert 0.45 < a <= 0.5, (pass_, a)
+        assert np.all(bw[1:] == np.arange(len(mid) - 1))

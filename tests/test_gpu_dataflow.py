@@ -83,14 +83,15 @@ def test_dataflow_split_plan_bitwise():
 
 def test_dataflow_full_size_mrf_bitwise():
     """The 256x256x8 Potts benchmark workload (16 + 16 waves, 75,684 tiles per pass): a few
-    iterations with each launch form, graph replay, multipliers and bounds bitwise equal."""
+    iterations with each launch form (waves, dataflow, two-branch waves), graph replay, multipliers
+    and bounds bitwise equal."""
     import torch
 
     ilp = I.config(2)
     plan = B.Plan(B.Problem.from_ilp(ilp))
     print(f"[dataflow full] tiles {plan.stats.fwd_tiles}+{plan.stats.bwd_tiles}", flush=True)
     res = []
-    for mode, chunk in ((0, 0), (1, 1), (1, 4)):
+    for mode, chunk in ((0, 0), (1, 1), (1, 4), (2, 0)):
         s = B.Solver(plan)
         s.set_launch(mode, chunk)
         s.iterate(3)
@@ -104,7 +105,7 @@ def test_dataflow_full_size_mrf_bitwise():
 
 def test_dataflow_launch_arguments():
     s = B.Solver(B.Plan(B.Problem.from_ilp(I.config(1))))
-    for bad in ((2, 0), (1, -1), (1, 5000)):
+    for bad in ((3, 0), (-1, 0), (1, -1), (1, 5000)):
         with pytest.raises(B.BddmpError) as e:
             s.set_launch(*bad)
         assert e.value.code == -1
@@ -116,9 +117,10 @@ def test_dataflow_launch_arguments():
     rows = [([0, k], [1, 1], 1, 1) for k in range(1, 301)]
     big = B.Solver(B.Plan(B.Problem.from_ilp(I.from_rows(301, np.ones(301), rows))))
     assert big.plan.stats.dataflow == 0
-    with pytest.raises(B.BddmpError) as e:
-        big.set_launch(1, 0)
-    assert e.value.code == -1
+    for mode in (1, 2):
+        with pytest.raises(B.BddmpError) as e:
+            big.set_launch(mode, 0)
+        assert e.value.code == -1
 
 
 def test_dataflow_wait_bound_reports_device_error(monkeypatch):

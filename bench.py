@@ -16,8 +16,9 @@ giving d LB_alpha / d c) on Potts 128x128 with 4 labels, 50 iterations, alpha in
 against plain min-plus iterations on the same instance.
 
 batched_vs_plain: the batched workload (256 tomography and tracking instances of uneven size) in
-one schedule against the same instances run one after another through their own plans; a sample of
-instances is compared bitwise.
+one schedule (wave-group launches, 256 consecutive waves per launch; one launch per wave and the
+dataflow launch alongside) against the same instances run one after another through their own
+plans; a sample of instances is compared bitwise.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload potts256x256_L8] [--no-batched]
 """
@@ -61,29 +62,30 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload: str):
-    """HBM bytes per launch of the wave kernels from the committed counter summary, or None when the
-    summary is missing or was taken on different kernel sources."""
+def committed_traffic(workload: str, kernel: str = ""):
+    """HBM bytes per launch of the update kernels (kernel "": one launch per wave; "group_": the
+    wave-group launch) from the committed counter summary, or None when the summary is missing,
+    lacks them or was taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", f"wave_kernels_{workload}.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         if line.startswith("traffic source_hash="):
             kv = dict(tok.split("=", 1) for tok in line.split()[1:])
-            if kv.get("source_hash") != kernel_source_hash():
+            if kv.get("source_hash") != kernel_source_hash() or f"{kernel}fwd_bytes_per_launch" not in kv:
                 return None
-            return {"fwd": float(kv["fwd_bytes_per_launch"]), "bwd": float(kv["bwd_bytes_per_launch"])}
+            return {"fwd": float(kv[f"{kernel}fwd_bytes_per_launch"]), "bwd": float(kv[f"{kernel}bwd_bytes_per_launch"])}
     return None
 
 
-def roofline_of(kt, traffic_rec):
-    """The dominant wave kernel class (the pass direction with the larger summed time) priced against
-    MI355X HBM peak: model bytes per launch over the average launch time (HIP events around whole
-    passes on the solver's stream); traffic from the committed counter summary, or None."""
+def roofline_of(kt, traffic_rec, kernel="wave_kernel"):
+    """The dominant update kernel class (the pass direction with the larger summed time) priced
+    against MI355X HBM peak: model bytes per launch over the average launch time (HIP events around
+    whole passes on the solver's stream); traffic from the committed counter summary, or None."""
     if kt["fwd_ms"] >= kt["bwd_ms"]:
-        kname, kms, kb, kl = "wave_kernel<fwd,update>", kt["fwd_ms"], kt["fwd_bytes"], kt["fwd_launches"]
+        kname, kms, kb, kl = f"{kernel}<fwd,update>", kt["fwd_ms"], kt["fwd_bytes"], kt["fwd_launches"]
     else:
-        kname, kms, kb, kl = "wave_kernel<bwd,update>", kt["bwd_ms"], kt["bwd_bytes"], kt["bwd_launches"]
+        kname, kms, kb, kl = f"{kernel}<bwd,update>", kt["bwd_ms"], kt["bwd_bytes"], kt["bwd_launches"]
     achieved = (kb / kl) / ((kms / kl) * 1e-3) / 1e9
     traffic = None if traffic_rec is None else traffic_rec["fwd" if "fwd" in kname else "bwd"]
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -134,25 +136,27 @@ def batched_vs_plain(args, B, I, torch):
     log(f"[bench] batched: {n} instances, nodes={st.n_nodes} incidences={st.n_incidences} "
         f"waves={st.waves_fwd}+{st.waves_bwd} plan {plan_s:.1f}s")
     bs = B.Solver(bp)
-    bs.iterate(1)
     T = args.batch_iters
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bs.iterate(T)
-    torch.cuda.synchronize()
-    batched_ms = (time.perf_counter() - t0) * 1e3 / T
-    # the dominant wave kernel of the batched schedule against HBM peak (events around whole
-    # passes, as for the main workload), and the dataflow launch of the same passes
-    kt = bs.time_kernels(3)
-    roofline = roofline_of(kt, committed_traffic(f"batch{n}"))
-    bs.set_launch(1, 1)
-    bs.iterate(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bs.iterate(T)
-    torch.cuda.synchronize()
-    dataflow_ms = (time.perf_counter() - t0) * 1e3 / T
-    bs.set_launch(0, 0)
+
+    def timed(mode, chunk):
+        bs.set_launch(mode, chunk)
+        bs.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs.iterate(T)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / T
+
+    # one launch per wave, then wave-group launches (args.batch_group_waves consecutive waves per
+    # launch; the leg's figure), each with its dominant kernel against HBM peak (events around
+    # whole passes, as for the main workload), then the dataflow launch of the same passes
+    G = args.batch_group_waves
+    wave_ms = timed(0, 0)
+    wave_roofline = roofline_of(bs.time_kernels(3), committed_traffic(f"batch{n}"))
+    batched_ms = timed(3, G)
+    roofline = roofline_of(bs.time_kernels(3), committed_traffic(f"batch{n}", "group_"), "group_kernel")
+    dataflow_ms = timed(1, 1)
+    bs.set_launch(3, G)
     # bitwise check on a sample: the same iterations from the start, batched and plain
     Tc = 5
     bs.reset()
@@ -188,7 +192,9 @@ def batched_vs_plain(args, B, I, torch):
     return {"workload": f"batch{n}: tomography P~U{{32..128}} (even positions) + tracking D~U{{200..2000}}",
             "instances": n, "n_nodes": int(st.n_nodes), "n_incidences": int(st.n_incidences),
             "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
+            "launch": f"wave groups: {G} consecutive waves per launch (launch mode 3)",
             "batched_ms_per_iter": batched_ms, "plain_ms_per_iter": plain_ms,
+            "wave_launch_ms_per_iter": wave_ms, "wave_launch_roofline": wave_roofline,
             "speedup": plain_ms / batched_ms if kp > 0 else None,
             "batched_arc_updates_per_s": arcs / (batched_ms * 1e-3),
             "plain_arc_updates_per_s": arcs / (plain_ms * 1e-3) if kp > 0 else None,
@@ -367,6 +373,8 @@ def main():
                     help="run only this comparison and print its object (profiling)")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--batch-group-waves", type=int, default=256,
+                    help="consecutive waves per wave-group launch in the batched leg (1..256)")
     ap.add_argument("--batch-plain-iters", type=int, default=3,
                     help="timed iterations per instance of the one-by-one comparison (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

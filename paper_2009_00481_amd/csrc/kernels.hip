@@ -726,6 +726,32 @@ __device__ __forceinline__ void set_priority(uint32_t p) {
   }
 }
 
+// Wait until the flags of the tiles tile record (ra, rb) depends on hold gen: the first wavefront's
+// lanes poll them with coherent loads, each at most spin_limit times (past it the error word is set
+// and the wait ends); then the workgroup's barrier, after which its lanes read the messages with
+// coherent loads (no cache holds a stale copy for them to hit).
+__device__ __forceinline__ void wait_deps(const int4 ra, const int4 rb, const int32_t *dep_list, const uint32_t *flags,
+                                          uint32_t gen, uint32_t spin_limit, uint32_t *err) {
+  const int nd = int((uint32_t(ra.z) >> 8) & 0x1FFu);
+  if (!nd) return;
+  const int s = int(threadIdx.x);
+  if (s < 64) {
+    for (int e = s; e < nd; e += 64) {
+      const int u = nd <= 4 ? (e == 0 ? rb.x : (e == 1 ? rb.y : (e == 2 ? rb.z : rb.w))) : dep_list[ra.w + e];
+      const uint32_t *f = flags + u;
+      uint32_t spins = 0u;
+      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+        if (++spins > spin_limit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int DIR, bool NARROW_PLAN>
 __global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(NARROW_PLAN ? 8 : 6)))
 void pass_kernel(const Dev D, const PassArgs A) {
@@ -762,26 +788,7 @@ void pass_kernel(const Dev D, const PassArgs A) {
       const int t = A.qtile[q0 + j];
       const int4 ra = A.trec[2 * t], rb = A.trec[2 * t + 1];
       const uint32_t info = uint32_t(ra.z);
-      const int nd = int((info >> 8) & 0x1FFu);
-      if (nd) {
-        if (s < 64) {
-          for (int e = s; e < nd; e += 64) {
-            const int u = nd <= 4 ? (e == 0 ? rb.x : (e == 1 ? rb.y : (e == 2 ? rb.z : rb.w))) : A.dep_list[ra.w + e];
-            const uint32_t *f = A.flags + u;
-            uint32_t spins = 0u;
-            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
-              if (++spins > A.spin_limit) {
-                atomicOr(A.ctl + kPassErr, 1u);
-                break;
-              }
-              __builtin_amdgcn_s_sleep(1);
-            }
-          }
-        }
-        // the polls returned before any lane passes the barrier; the messages are then read with
-        // coherent loads (no cache holds a stale copy for them to hit)
-        __syncthreads();
-      }
+      wait_deps(ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr);
       const bool list = (info & 2u) != 0u;
       set_priority((info >> 2) & 3u);
       if constexpr (NARROW_PLAN) {
@@ -809,6 +816,55 @@ void pass_kernel(const Dev D, const PassArgs A) {
       __hip_atomic_store(A.ctl + kPassGen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+}
+
+// Several consecutive waves of an update pass in one launch (Alg. "Min-marginal averaging", part of
+// the forward or the backward pass), one workgroup per tile. A wave's workgroups form one block
+// range, its tiles in the XCD-aware order of the wave launches; the tiles of the launch's first
+// wave read only what earlier launches wrote, those of a later wave first wait for the flags of the
+// tiles they read from (the plan's dependency lists).
+//
+// Progress: each XCD receives every eighth workgroup and dispatches its workgroups in block order,
+// so on every XCD all workgroups of a wave are dispatched before any of the next wave. A workgroup
+// waits only for tiles of earlier waves. By induction over the launch's waves: the first wave never
+// waits; when every tile of waves before i finishes, a workgroup of wave i either runs or waits for
+// one of them, and an XCD whose compute units are full of waiting workgroups of wave i has
+// dispatched all of its own earlier-wave workgroups, which finish. Each wait is bounded all the same
+// (error word, then the workgroup goes on), so the kernel always exits.
+//
+// Publication: a tile's messages are written and read with coherent agent-scope accesses (msg_ld /
+// msg_st). A tile of a wave that later waves of the launch may read waits until its stores are
+// complete (vmcnt 0) before one lane stores the flag; a tile of the launch's last wave stores its
+// flag at once (its readers run in later launches, after this one has ended).
+template <int DIR, bool NARROW_PLAN>
+__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(NARROW_PLAN ? 8 : 6)))
+void group_kernel(const Dev D, const GroupArgs A) {
+  __shared__ std::conditional_t<NARROW_PLAN, WaveLds<true>, WaveLdsMixed> sh;
+  const int s = int(threadIdx.x), b = int(blockIdx.x);
+  // the workgroup's wave: the largest i with wofs[i] <= b (wofs ascending, wofs[0] = 0)
+  int i = 0;
+  for (int step = kGroupMaxWaves / 2; step > 0; step >>= 1)
+    if (i + step < A.nw && A.wofs[i + step] <= b) i += step;
+  const int k = xcd_tile(b - A.wofs[i], A.wofs[i + 1] - A.wofs[i]);
+  if (k >= A.tofs[i + 1] - A.tofs[i]) return;
+  const int t = A.tofs[i] + k;
+  const uint32_t gen = uint32_t(*D.hist_n) | 0x80000000u;
+  const int4 ra = A.trec[2 * t], rb = A.trec[2 * t + 1];
+  const uint32_t info = uint32_t(ra.z);
+  if (i > 0) wait_deps(ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr);
+  const bool list = (info & 2u) != 0u;
+  if constexpr (NARROW_PLAN) {
+    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+  } else if (info & 1u) {
+    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+  } else {
+    wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+  }
+  if (i + 1 < A.nw) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+  }
+  if (s == 0) __hip_atomic_store(A.flags + t, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One variable with more than kTile rows per workgroup (its layers are the whole tile).
@@ -1144,6 +1200,19 @@ hipError_t pass_blocks_per_cu(int dir, bool narrow_plan, int *blocks) {
                                : (narrow_plan ? reinterpret_cast<const void *>(pass_kernel<kBwd, true>)
                                               : reinterpret_cast<const void *>(pass_kernel<kBwd, false>));
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kTile, 0);
+}
+
+template <int DIR, bool NARROW_PLAN>
+static hipError_t group_dispatch(const Dev &D, const GroupArgs &A, hipStream_t s) {
+  hipLaunchKernelGGL((group_kernel<DIR, NARROW_PLAN>), dim3(A.wofs[A.nw]), dim3(kTile), 0, s, D, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_group(int dir, bool narrow_plan, const Dev &D, const GroupArgs &A, hipStream_t s) {
+  if (A.nw < 1 || A.nw > kGroupMaxWaves) return hipErrorInvalidValue;
+  if (A.wofs[A.nw] <= 0) return hipSuccess;
+  if (dir == kFwd) return narrow_plan ? group_dispatch<kFwd, true>(D, A, s) : group_dispatch<kFwd, false>(D, A, s);
+  return narrow_plan ? group_dispatch<kBwd, true>(D, A, s) : group_dispatch<kBwd, false>(D, A, s);
 }
 
 template <int DIR, int MODE>

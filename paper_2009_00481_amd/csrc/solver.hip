@@ -49,6 +49,9 @@ struct Solver {
   bool pipe = false;
   hipStream_t side = nullptr, cap_side = nullptr;
   std::vector<hipEvent_t> pipe_ev;
+  // wave-group launches: waves per launch (0: off) and the bound of one dependency wait
+  int group_waves = 0;
+  uint32_t group_spin = 0;
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gexec_wrap) (void)hipGraphExecDestroy(gexec_wrap);
@@ -76,6 +79,10 @@ int32_t launched(hipError_t e, const char *what) { return e == hipSuccess ? BDDM
 // polls of one dependency flag before a wait of the dataflow launch gives up (each poll is a load
 // and a short sleep, about a microsecond: several seconds in all, far beyond any real wait)
 constexpr uint32_t kPassSpinLimit = 1u << 23;
+// The same for the wave-group launch, whose waits are for tiles of the same launch that were
+// dispatched before the waiting one (a quarter of a second or so), and the default waves per launch
+constexpr uint32_t kGroupSpinLimit = 1u << 18;
+constexpr int kGroupDefaultWaves = 4;
 
 // BDDMP_DEVICE if a dataflow launch gave up a wait (its error word is set; the stream is
 // synchronised by the caller before *err is read)
@@ -85,10 +92,10 @@ int32_t pass_error(uint32_t err) {
                                  "last reset are invalid");
 }
 
-// the turnaround and wrap-around launches fuse wave launches; the dataflow and two-branch launches
-// have none
-bool use_turn(const Solver &S) { return S.plan->fuse_turn && !S.dataflow && !S.pipe; }
-bool use_wrap(const Solver &S) { return S.plan->fuse_wrap && !S.dataflow && !S.pipe; }
+// the turnaround and wrap-around launches fuse wave launches; the dataflow, two-branch and
+// wave-group launches have none
+bool use_turn(const Solver &S) { return S.plan->fuse_turn && !S.dataflow && !S.pipe && !S.group_waves; }
+bool use_wrap(const Solver &S) { return S.plan->fuse_wrap && !S.dataflow && !S.pipe && !S.group_waves; }
 
 // NONFINITE unless every value of the device arrays (float or double, n each) is finite; checked on
 // the device, then the stream is synchronised to read the result.
@@ -185,6 +192,30 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
     if (int32_t rc = launched(launch_pass(dir, P.n_general == 0, S.pass_grid[p], S.D, S.pass[p], st), "pass kernel"))
       return rc;
     return tm.stop(st, S.pass[p].n_tiles > 0 ? 1 : 0);
+  }
+  if (S.group_waves && mode == kUpdate) {
+    // group_waves consecutive waves per launch, each wave's workgroups rounded up to a multiple of 8
+    const int p = dir == kFwd ? 0 : 1;
+    int launches = 0;
+    for (size_t w = 0; w < waves.size(); w += size_t(S.group_waves)) {
+      GroupArgs ga{};
+      ga.trec = S.pass[p].trec;
+      ga.dep_list = S.pass[p].dep_list;
+      ga.flags = S.pass[p].flags;
+      ga.ctl = S.pass[p].ctl;
+      ga.spin_limit = S.group_spin;
+      ga.nw = int32_t(std::min(waves.size() - w, size_t(S.group_waves)));
+      ga.tofs[0] = waves[w].tile_begin;
+      ga.wofs[0] = 0;
+      for (int i = 0; i < ga.nw; ++i) {
+        const WaveRange &wr = waves[w + size_t(i)];
+        ga.tofs[i + 1] = wr.tile_end;
+        ga.wofs[i + 1] = ga.wofs[i] + (wr.tile_end - wr.tile_begin + 7) / 8 * 8;
+      }
+      if (int32_t rc = launched(launch_group(dir, P.n_general == 0, S.D, ga, st), "wave-group kernel")) return rc;
+      launches += ga.wofs[ga.nw] > 0 ? 1 : 0;
+    }
+    return tm.stop(st, launches);
   }
   if (S.pipe && mode == kUpdate) {
     if (int32_t rc = pipe_pass(S, dir, st)) return rc;
@@ -644,9 +675,12 @@ int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj
 
 int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
   const Plan &P = *S.plan;
-  if (mode < 0 || mode > 2)
-    return set_error(BDDMP_INVALID_ARG, "launch mode must be 0 (wave launches), 1 (dataflow) or 2 (two-branch waves)");
+  if (mode < 0 || mode > 3)
+    return set_error(BDDMP_INVALID_ARG,
+                     "launch mode must be 0 (wave launches), 1 (dataflow), 2 (two-branch waves) or 3 (wave groups)");
   if (chunk < 0 || chunk > 4096) return set_error(BDDMP_INVALID_ARG, "chunk must be 0 (default) .. 4096");
+  if (mode == 3 && chunk > kGroupMaxWaves)
+    return set_error(BDDMP_INVALID_ARG, "waves per wave-group launch must be 0 (default) .. " + std::to_string(kGroupMaxWaves));
   if (mode != 0 && !P.pers_ok)
     return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow or two-branch launch");
   if (mode == 2) {
@@ -678,13 +712,16 @@ int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
   }
   S.dataflow = mode == 1;
   S.pipe = mode == 2;
+  S.group_waves = mode == 3 ? (chunk ? chunk : kGroupDefaultWaves) : 0;
+  S.group_spin = kGroupSpinLimit;
+  if (const char *e = std::getenv("BDDMP_PASS_SPIN_LIMIT")) S.group_spin = uint32_t(std::strtoul(e, nullptr, 10));
   drop_graph(S);
   return BDDMP_OK;
 }
 
 int32_t solver_get_launch(const Solver &S, int32_t *mode, int32_t *chunk) {
-  if (mode) *mode = S.dataflow ? 1 : (S.pipe ? 2 : 0);
-  if (chunk) *chunk = S.pass[0].chunk;
+  if (mode) *mode = S.dataflow ? 1 : (S.pipe ? 2 : (S.group_waves ? 3 : 0));
+  if (chunk) *chunk = S.group_waves ? S.group_waves : S.pass[0].chunk;
   return BDDMP_OK;
 }
 

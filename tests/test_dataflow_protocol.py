@@ -224,3 +224,95 @@ def test_two_branch_split_is_balanced_on_a_grid_mrf():
         a = (mid - beg[:-1]).sum() / (beg[-1] - beg[0])
         assert 0.45 < a <= 0.5, (pass_, a)
         assert np.all(bw[1:] == np.arange(len(mid) - 1))
+
+
+def _xcd_tile(b, n, xcds=8):
+    q, r = n // xcds, n % xcds
+    x, k = b % xcds, b // xcds
+    return x * q + min(x, r) + k
+
+
+def _group_launch(ptr, lst, beg, w0, nw, slots, rng, done_at):
+    """One wave-group launch (waves w0 .. w0 + nw - 1) under the hardware's dispatch: workgroup b
+    goes to XCD b mod 8, each XCD dispatches its own workgroups in block order into `slots` slots;
+    running workgroups advance in random order. A workgroup of the launch's first wave runs at once;
+    one of a later wave waits until every tile it depends on is done. Returns False on a deadlock."""
+    tofs = [beg[w0 + i] for i in range(nw + 1)]
+    wofs = [0]
+    for i in range(nw):
+        wofs.append(wofs[-1] + (tofs[i + 1] - tofs[i] + 7) // 8 * 8)
+    queues = [[b for b in range(wofs[-1]) if b % 8 == x] for x in range(8)]
+    running = [[] for _ in range(8)]
+    while any(queues) or any(running):
+        for x in range(8):
+            while queues[x] and len(running[x]) < slots:
+                running[x].append(queues[x].pop(0))
+        ready = []
+        for x in range(8):
+            for b in running[x]:
+                i = max(j for j in range(nw) if b >= wofs[j])
+                k = _xcd_tile(b - wofs[i], wofs[i + 1] - wofs[i])
+                t = tofs[i] + k
+                if k >= tofs[i + 1] - tofs[i]:
+                    ready.append((x, b, None))
+                elif i == 0 or all(u in done_at for u in lst[ptr[t]:ptr[t + 1]]):
+                    ready.append((x, b, t))
+        if not ready:
+            return False
+        x, b, t = ready[rng.integers(len(ready))]
+        if t is not None:
+            assert t not in done_at
+            for u in lst[ptr[t]:ptr[t + 1]]:
+                assert u in done_at, f"tile {t} ran before {u}"
+            done_at[t] = len(done_at)
+        running[x].remove(b)
+    return True
+
+
+@pytest.mark.parametrize("name", ["cfg1", "rand", "batch"])
+@pytest.mark.parametrize("group", [2, 3, 8])
+def test_wave_group_launch_runs_every_tile_after_its_dependencies(name, group):
+    """The wave-group launch's block mapping (every wave's workgroups a block range rounded up to a
+    multiple of 8, tiles in XCD order inside it) under per-XCD in-order dispatch with as few as one
+    slot per XCD: every tile runs once, after every tile it reads from, and no launch deadlocks.
+    Control: with the waves' block ranges interleaved (not the launch's mapping) one slot per XCD
+    can deadlock."""
+    plan = _plans()[name]()
+    rng = np.random.default_rng(group)
+    for pass_ in (0, 1):
+        ptr, lst, _ = plan.tile_deps(pass_)
+        beg, _, _ = plan.wave_split(pass_)
+        W = len(beg) - 1
+        for slots in (1, 3):
+            done_at = {}
+            for w0 in range(0, W, group):
+                assert _group_launch(ptr, lst, beg, w0, min(group, W - w0), slots, rng, done_at), (pass_, w0, slots)
+            assert sorted(done_at) == list(range(len(ptr) - 1))
+
+
+def test_wave_group_control_reversed_waves_deadlock():
+    """Control: a launch whose later wave sits in lower blocks than the wave it depends on (the
+    order the mapping forbids) deadlocks with one slot per XCD."""
+    # two waves of 8 tiles; tile 8 + j depends on tile j; blocks 0..7 hold wave 1, 8..15 wave 0
+    def launch(slots):
+        queues = [[b for b in range(16) if b % 8 == x] for x in range(8)]
+        running = [[] for _ in range(8)]
+        done = set()
+        while any(queues) or any(running):
+            for x in range(8):
+                while queues[x] and len(running[x]) < slots:
+                    running[x].append(queues[x].pop(0))
+            moved = False
+            for x in range(8):
+                for b in list(running[x]):
+                    t = 8 + b if b < 8 else b - 8   # reversed: wave 1 first
+                    if t < 8 or (t - 8) in done:
+                        done.add(t)
+                        running[x].remove(b)
+                        moved = True
+            if not moved:
+                return False
+        return True
+
+    assert not launch(1)
+    assert launch(2)

@@ -1,0 +1,107 @@
+"""GPU tests of the wave-group launches (bddmp_solver_set_launch mode 3): several consecutive waves
+of a pass per launch, one workgroup per tile, a later wave's tiles waiting only for the flags of
+the tiles they read from. Each tile runs the same operations as with one launch per wave, after
+every tile it reads from, so every output must be bitwise equal to the wave launches: multipliers,
+bounds, min-marginals, rounded primal, per-instance bounds; with graph replay and eager launches;
+narrow, wide, list, batched and split plans; 2, 3 and 8 waves per launch; switching launch forms
+between calls. A wait that exceeds its bound is forced from the host (a spin limit of zero) and
+must come back as DEVICE from the next bound read, every kernel exiting normally."""
+import numpy as np
+import pytest
+
+from paper_2009_00481_amd import binding as B
+from paper_2009_00481_amd import instances as I
+from test_gpu_dataflow import _cases, _run, _same
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_wave_groups_equal_wave_launches_bitwise(name):
+    insts = _cases()[name]()
+    T = 4
+    print(f"[wave groups] {name}", flush=True)
+    plan, ref = _run(insts, 0, 0, True, T)
+    for graphs, g in ((True, 2), (True, 3), (False, 8)):
+        _, got = _run(insts, 3, g, graphs, T)
+        _same(ref, got, (name, graphs, g))
+
+
+def test_wave_groups_split_plan_bitwise():
+    insts = [I.tomography(10, seed=5, unary="normal"), I.tracking(300, seed=9)]
+    plan, ref = _run(insts, 0, 0, True, 3, split=3)
+    assert plan.stats.n_cuts > 0
+    _, got = _run(insts, 3, 4, True, 3, split=3)
+    _same(ref, got, "split")
+
+
+def test_wave_groups_full_size_mrf_bitwise():
+    """The 256x256x8 Potts benchmark workload with 2, 4 and 8 waves per launch: multipliers and
+    bounds after 3 iterations bitwise those of the wave launches."""
+    import torch
+
+    plan = B.Plan(B.Problem.from_ilp(I.config(2)))
+    res = []
+    for mode, g in ((0, 0), (3, 2), (3, 4), (3, 8)):
+        print(f"[wave groups full] mode {mode} waves {g}", flush=True)
+        s = B.Solver(plan)
+        s.set_launch(mode, g)
+        s.iterate(3)
+        res.append((s.get_lambda().cpu().numpy(), s.lb_history(4)))
+        del s
+        torch.cuda.empty_cache()
+    for lam, hist in res[1:]:
+        assert np.array_equal(lam, res[0][0])
+        assert np.array_equal(hist, res[0][1])
+
+
+def test_wave_groups_switching_and_arguments():
+    import torch
+
+    plan = B.Plan(B.Problem.from_ilp(I.config("5sub")))
+    a, b = B.Solver(plan), B.Solver(plan)
+    for mode, g in ((3, 2), (1, 1), (3, 4), (0, 0), (2, 0), (3, 0)):
+        b.set_launch(mode, g)
+        assert b.launch()[0] == mode
+        if mode == 3:
+            assert b.launch()[1] == (g or 4)
+        a.iterate(3)
+        b.iterate(3)
+        assert np.array_equal(a.get_lambda().cpu().numpy(), b.get_lambda().cpu().numpy()), (mode, g)
+    assert np.array_equal(a.lb_history(19), b.lb_history(19))
+    with pytest.raises(B.BddmpError) as e:
+        b.set_launch(3, 257)
+    assert e.value.code == -1
+    torch.cuda.synchronize()
+
+
+def test_wave_groups_wait_bound_reports_device_error(monkeypatch):
+    """A spin limit of zero makes every wait that finds its dependency unfinished give up at once:
+    the kernel still exits, the error word is set, and lower_bound reports DEVICE (or, if no wait
+    found its dependency unfinished, the results are exact); a reset clears it."""
+    import torch
+
+    monkeypatch.setenv("BDDMP_PASS_SPIN_LIMIT", "0")
+    plan = B.Plan(B.Problem.from_ilp(I.config(5)))
+    s = B.Solver(plan)
+    s.set_launch(3, 8)
+    s.iterate(10)
+    ref = B.Solver(plan)
+    ref.iterate(10)
+    try:
+        lb = s.lower_bound()[0]
+        gave_up = False
+        assert lb == ref.lower_bound()[0]
+    except B.BddmpError as e:
+        assert e.code == -6
+        gave_up = True
+    print(f"[wave groups] a wait gave up: {gave_up}", flush=True)
+    monkeypatch.delenv("BDDMP_PASS_SPIN_LIMIT")
+    s.set_launch(3, 8)
+    s.reset()
+    ref.reset()
+    s.iterate(5)
+    ref.iterate(5)
+    assert np.array_equal(s.get_lambda().cpu().numpy(), ref.get_lambda().cpu().numpy())
+    assert s.lower_bound()[0] == ref.lower_bound()[0]
+    torch.cuda.synchronize()

@@ -75,6 +75,11 @@ typedef struct {
                              "0,0,0,0"); see bddmp_solver_set_groups                             */
   int32_t n_intervals;    /* Sec. 6 split: variable intervals per instance (0 or 1: no split)   */
   float split_gamma;      /* copy-arc step size gamma in (0, 1] (0: default 0.5)                 */
+  int32_t wave_align;     /* 0: each variable in its earliest wave (the longest chain of row
+                             predecessors before it); 1: in its latest (the longest chain after it
+                             ends with the last wave), so shorter instances of a batch start late.
+                             Both order every variable after its predecessors in each pass, so
+                             results are the same; only the schedule differs                     */
 } bddmp_options;
 
 typedef struct {

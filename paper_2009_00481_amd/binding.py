@@ -35,7 +35,7 @@ class BddmpError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("order_mode", C.c_int32), ("hist_cap", C.c_int32), ("node_budget", C.c_int64),
                 ("tile_work", C.c_int32), ("tiling", C.c_char_p), ("n_intervals", C.c_int32),
-                ("split_gamma", C.c_float)]
+                ("split_gamma", C.c_float), ("wave_align", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -468,8 +468,10 @@ class Plan:
     """A plan for one problem, or for several independent ones (``problem`` a list: batched)."""
 
     def __init__(self, problem, order_mode: int = 0, node_budget: int = 0, hist_cap: int = 4096,
-                 tiling: str | None = None, tile_work: int = 0, n_intervals: int = 0, split_gamma: float = 0.0):
+                 tiling: str | None = None, tile_work: int = 0, n_intervals: int = 0, split_gamma: float = 0.0,
+                 wave_align: int = 0):
         o = bddmp_options_default()
+        o.wave_align = wave_align
         o.tile_work = tile_work
         o.n_intervals = n_intervals
         o.split_gamma = split_gamma

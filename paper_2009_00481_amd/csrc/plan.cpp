@@ -481,6 +481,7 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   if (opt.n_intervals < 0) return set_error(BDDMP_INVALID_ARG, "negative n_intervals");
   if (!(opt.split_gamma == 0.0f || (opt.split_gamma > 0.0f && opt.split_gamma <= 1.0f)))
     return set_error(BDDMP_INVALID_ARG, "split_gamma must lie in (0, 1] (0: default)");
+  if (opt.wave_align != 0 && opt.wave_align != 1) return set_error(BDDMP_INVALID_ARG, "wave_align must be 0 or 1");
   P.split_k = opt.n_intervals > 1 ? opt.n_intervals : 0;
   P.split_gamma = opt.split_gamma > 0.0f ? opt.split_gamma : 0.5f;
   if (opt.tiling && !parse_groups(opt.tiling, P.gsel))
@@ -657,6 +658,19 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     }
     P.wave_b[i] = t + 1;
     P.Db = std::max(P.Db, t + 1);
+  }
+  // latest waves: a variable whose longest chain of row successors (its earliest backward wave)
+  // has length h can run as late as forward wave D + 1 - h, D the longest chain (Df = Db); a
+  // predecessor's chain is longer, so its wave is earlier. The same holds for the backward pass.
+  if (P.Df != P.Db) return set_error(BDDMP_INVALID_ARG, "internal: forward and backward chain lengths differ");
+  if (opt.wave_align == 1) {
+    const int32_t D = P.Df;
+    for (int32_t i = 0; i < n; ++i)
+      if (P.var_nj[i]) {
+        const int32_t f = P.wave_f[i];
+        P.wave_f[i] = D + 1 - P.wave_b[i];
+        P.wave_b[i] = D + 1 - f;
+      }
   }
 
   // Groups of instances for the dataflow launch: instances never share a row, so a tile whose

@@ -27,11 +27,12 @@ def _cases():
     }
 
 
-def _run(insts, mode, chunk, graphs, T, split=0):
+def _run(insts, mode, chunk, graphs, T, split=0, wave_align=0):
     import torch
 
     probs = [B.Problem.from_ilp(q) for q in insts]
-    plan = B.Plan(probs if len(probs) > 1 else probs[0], hist_cap=max(64, T + 8), n_intervals=split)
+    plan = B.Plan(probs if len(probs) > 1 else probs[0], hist_cap=max(64, T + 8), n_intervals=split,
+                  wave_align=wave_align)
     s = B.Solver(plan)
     s.set_graphs(graphs)
     s.set_launch(mode, chunk)

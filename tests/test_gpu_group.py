@@ -27,6 +27,17 @@ def test_wave_groups_equal_wave_launches_bitwise(name):
         _same(ref, got, (name, graphs, g))
 
 
+def test_latest_waves_equal_earliest_waves_bitwise():
+    """A batch planned with every variable in its latest wave (wave_align 1), with one launch per
+    wave and with wave groups, against the default plan's wave launches: the same multipliers,
+    bounds, min-marginals, rounded primal and instance bounds."""
+    insts = _cases()["batch"]()
+    _, ref = _run(insts, 0, 0, True, 4)
+    for mode, g in ((0, 0), (3, 4), (3, 256)):
+        _, got = _run(insts, mode, g, True, 4, wave_align=1)
+        _same(ref, got, ("latest waves", mode, g))
+
+
 def test_wave_groups_split_plan_bitwise():
     insts = [I.tomography(10, seed=5, unary="normal"), I.tracking(300, seed=9)]
     plan, ref = _run(insts, 0, 0, True, 3, split=3)

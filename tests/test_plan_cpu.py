@@ -118,6 +118,49 @@ def test_waves_are_the_dependency_levels(seed):
     _check_waves(ilp, _plan(ilp))
 
 
+def _check_latest_waves(ilp, asap, alap):
+    """The latest waves (wave_align 1) against the earliest ones of the same problem: forward wave
+    D + 1 - (earliest backward wave) and backward wave D + 1 - (earliest forward wave), every
+    variable after each of its row predecessors (forward) or successors (backward), each row's
+    variables in distinct waves."""
+    wf0, wb0 = asap.waves()
+    wf1, wb1 = alap.waves()
+    D = asap.stats.waves_fwd
+    assert alap.stats.waves_fwd == D and alap.stats.waves_bwd == D
+    inrow = wf0 > 0
+    assert np.array_equal(wf1[inrow], D + 1 - wb0[inrow]) and np.array_equal(wb1[inrow], D + 1 - wf0[inrow])
+    assert np.all(wf1[~inrow] == 0) and np.all(wb1[~inrow] == 0)
+    order = asap.order()
+    rank = np.empty(ilp.n, np.int64)
+    rank[order] = np.arange(ilp.n)
+    for j in range(ilp.m):
+        c, a, _, _ = ilp.row(j)
+        vs = sorted((int(v) for v in c[a != 0]), key=lambda v: rank[v])
+        for t in range(1, len(vs)):
+            assert wf1[vs[t]] > wf1[vs[t - 1]] and wb1[vs[t - 1]] > wb1[vs[t]]
+    # no wave is empty
+    assert set(wf1[inrow].tolist()) == set(range(1, D + 1)) and set(wb1[inrow].tolist()) == set(range(1, D + 1))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_latest_waves_random(seed):
+    ilp = I.random_ilp(40, 30, kmax=6, seed=seed)
+    _check_latest_waves(ilp, _plan(ilp), _plan(ilp, wave_align=1))
+
+
+def test_latest_waves_batch_start_shorter_instances_late():
+    """In a batch, an instance with a shorter longest chain than the batch's has its first
+    variables in a later forward wave than 1; the deepest instance keeps wave 1."""
+    qs = [I.tracking(250, seed=1), I.config(1), I.tomography(6, seed=0)]
+    asap = B.Plan([B.Problem.from_ilp(q) for q in qs])
+    alap = B.Plan([B.Problem.from_ilp(q) for q in qs], wave_align=1)
+    _check_latest_waves(I.concat(qs), asap, alap)
+    voff, _, _ = alap.instances()
+    wf1, _ = alap.waves()
+    first = [int(wf1[voff[k]:voff[k + 1]][wf1[voff[k]:voff[k + 1]] > 0].min()) for k in range(len(qs))]
+    assert min(first) == 1 and max(first) > 1
+
+
 def test_waves_configs():
     for ilp in (I.config(1), I.graph_matching(300, 300, 10, 3000, seed=1)):
         _check_waves(ilp, _plan(ilp))
@@ -180,6 +223,10 @@ def test_errors():
     with pytest.raises(B.BddmpError) as e:
         _plan(I.config(1), node_budget=1000)
     assert e.value.code == -3
+    for bad in (-1, 2):
+        with pytest.raises(B.BddmpError) as e:
+            _plan(I.config(1), wave_align=bad)
+        assert e.value.code == -1
     p = B.Problem(3, np.zeros(3))
     with pytest.raises(B.BddmpError) as e:
         p.set_order([0, 0, 1])

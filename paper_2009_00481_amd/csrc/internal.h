@@ -42,6 +42,9 @@ constexpr int kWidthClasses = 4;
 // A tile closes early once its general layers hold this many nodes (own plus child level), so
 // that tiles with wide levels carry comparable work (default; options.tile_work overrides).
 constexpr int64_t kTileWideWork = 2048;
+// nodes of a tile's general own levels, and of their child levels, that the node-parallel (flat)
+// path stages at most (kFlatCap / kTile per lane)
+constexpr int kFlatCap = 2048;
 // Packed in-arcs of a next-level node with at most two (two in-arc codes, kNoArc16 for none);
 // kManyInArcs marks a node with more, whose in-arcs are read from the offset lists.
 constexpr uint32_t kNoArc16 = 0xFFFFu, kManyInArcs = 0xFFFFFFFFu;
@@ -90,6 +93,7 @@ struct Problem {
 struct ArenaLayout {
   size_t meta, child, parent, lam, mf, mbc, garcs, grec, gnb, rbeg, rin, rarc, canon_of, layer_of, layer_var, root_slot;
   size_t fdep_list, bdep_list, ftrec, btrec, fqptr, fqtile, bqptr, bqtile, fflag, bflag, pctl;
+  size_t fgt, bgt, fgm, bgm;
   size_t fwd_tiles, bwd_tiles, bwd_list, fwd_big, bwd_big;
   size_t bdd_canon_off, cost, var_first, var_nj;
   size_t d_fresh, mbuf, xbuf, part, lbpart, lb_hist, scal;
@@ -212,6 +216,14 @@ struct Plan {
     int32_t mid, b_wait;
   };
   std::vector<WaveSplit> fsplit, bsplit;
+  // Node maps of the node-parallel (flat) path: per normal tile of each pass two words, the byte
+  // offset of the tile's maps in the pass's map array (a multiple of 16) and its general own nodes
+  // | child nodes << 16, or {-1, 0} when it has no general layer or its levels exceed the flat stage.
+  // The maps hold, per own node and then per child node (the concatenated levels of the tile's
+  // general layers in position order), the rank of the node's layer among the tile's general
+  // layers; each tile's maps are padded to a multiple of 16 bytes.
+  std::vector<int32_t> fgt, bgt;
+  std::vector<uint8_t> fgm, bgm;
   // lanes per general layer for each tile width class (log2, 4 bits each), and the normal tiles
   // of each class over both passes
   uint32_t gsel = kDefaultGsel;

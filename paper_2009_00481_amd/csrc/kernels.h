@@ -64,6 +64,10 @@ struct Dev {
   const int32_t *inst_cut, *inst_cut_idx;  // each instance's cut records (offsets, record indices)
   const int32_t *exit_rec;    // per layer: the cut record it is the exit layer of, or -1 (null: no split)
   float gamma;
+  // node maps of the flat path per pass (see Plan): per tile {byte offset of its maps or -1, own |
+  // child nodes << 16}, and the maps (layer rank of each staged node, 16-byte aligned per tile)
+  const int2 *fgt, *bgt;
+  const uint8_t *fgm, *bgm;
 };
 
 // One wave: nt normal tiles from tile0 of the pass's tile list (dir kFwd / kBwd, mode as above).

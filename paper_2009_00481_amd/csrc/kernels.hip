@@ -259,47 +259,7 @@ __device__ __forceinline__ float group_bstep(const Dev &D, const GenTile &T, int
 // Flat path: the tile's general nodes spread over all lanes (node t of the concatenated own
 // levels, kFlatR per lane), with the child levels' backward messages and the own levels' forward
 // messages staged in LDS. A layer's min-marginals are integer minima in LDS (exact).
-constexpr int kFlatCap = 2048;             // own nodes and child nodes a tile may stage
 constexpr int kFlatR = kFlatCap / kTile;   // nodes per lane
-
-// The layers holding the lane's first N nodes s, s + kTile, ... (clamped to total - 1) of a tile's
-// concatenated levels: for node t, the largest k < n with off[k] <= t (off: exclusive prefix sums
-// of the levels' widths, so non-decreasing with off[0] = 0; a level of width 0 repeats its
-// successor's offset and is passed over). Fixed-step binary searches that advance together, so
-// their LDS reads are in flight at the same time: the lane waits for 8 read latencies, not 8 N.
-template <int N>
-__device__ __forceinline__ void layers_of_slots(const int *off, int n, int total, int s, int *k) {
-  int t[N];
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    t[r] = min(s + r * kTile, total - 1);
-    k[r] = 0;
-  }
-#pragma unroll
-  for (int step = kTile / 2; step > 0; step >>= 1) {
-    int v[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = off[k[r] + step];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-      if (k[r] + step < n && v[r] <= t[r]) k[r] += step;
-  }
-}
-
-// the same for the first R slots, R = ceil(total / kTile) (uniform over the workgroup; 0 .. kFlatR)
-__device__ __forceinline__ void slot_layers(const int *off, int n, int total, int s, int *k) {
-  switch ((total + kTile - 1) / kTile) {
-    case 1: layers_of_slots<1>(off, n, total, s, k); break;
-    case 2: layers_of_slots<2>(off, n, total, s, k); break;
-    case 3: layers_of_slots<3>(off, n, total, s, k); break;
-    case 4: layers_of_slots<4>(off, n, total, s, k); break;
-    case 5: layers_of_slots<5>(off, n, total, s, k); break;
-    case 6: layers_of_slots<6>(off, n, total, s, k); break;
-    case 7: layers_of_slots<7>(off, n, total, s, k); break;
-    case 8: layers_of_slots<8>(off, n, total, s, k); break;
-    default: break;
-  }
-}
 
 // Minimum of v over the lanes j - back .. j of the wavefront (the lanes of lane j's run so far;
 // back <= lane), by DPP moves: shifts by 1, 2, 4 and 8 inside each row of 16 lanes, then the last
@@ -338,10 +298,10 @@ struct WaveLds {
   // are read before the update begins (fewer LDS bytes per workgroup, more workgroups per CU)
   float share_n[NARROW_ONLY ? kTile : 1];
   int nf_n[NARROW_ONLY ? kTile : 1];
-  // flat path: the next levels' backward messages; in a forward tile, once the min-marginals are
-  // taken, the own levels' forward messages for the pull (one array serves both, so that more
-  // workgroups fit a CU's LDS)
-  float cb[NARROW_ONLY ? 1 : kFlatCap];
+  // flat path: first the tile's node maps, then the next levels' backward messages; in a forward
+  // tile, once the min-marginals are taken, the own levels' forward messages for the pull (one
+  // array serves all three, so that more workgroups fit a CU's LDS)
+  alignas(16) float cb[NARROW_ONLY ? 1 : kFlatCap];
 };
 
 // One tile of a wave: tix indexes the pass's tile list (dir DIR), btix the backward tile of the same
@@ -387,6 +347,17 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
   ly.tgt = -1;
   int4 grec = make_int4(0, 0, 0, 0);
   int2 gnb = make_int2(-1, -1);
+  // flat path (the tile's width class selects it and the tile has node maps, i.e. its general
+  // levels fit the stage): the tile's node maps, 16 bytes per lane, loaded with the layer records
+  const int mode = NARROW_ONLY ? 0 : int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
+  int2 gtr = make_int2(-1, 0);
+  if constexpr (!NARROW_ONLY)
+    if (mode == int(kFlat)) gtr = (DIR == kFwd ? D.fgt : D.bgt)[tix];
+  const bool flat = !NARROW_ONLY && gtr.x >= 0;
+  const bool map_lane = flat && 16 * s < (gtr.y & 0xFFFF) + int(uint32_t(gtr.y) >> 16);
+  uint4 gmp = make_uint4(0u, 0u, 0u, 0u);
+  if constexpr (!NARROW_ONLY)
+    if (map_lane) gmp = *reinterpret_cast<const uint4 *>((DIR == kFwd ? D.fgm : D.bgm) + gtr.x + 16 * s);
   if (active) {
     const int L = (DIR == kBwd && LIST && list) ? D.bwd_list[p0 + s] : p0 + s;
     if (!NARROW_ONLY) {
@@ -395,10 +366,12 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
     }
     ly.begin(D, L);
   }
+  // the maps into the stage (free until the staging below; the width scan's barriers publish them)
+  if constexpr (!NARROW_ONLY)
+    if (map_lane) reinterpret_cast<uint4 *>(s_cb)[s] = gmp;
 
   bool gen = false;
-  int ngen = 0, myk = 0, mode = 0, G = 1, TW = 0, TC = 0;
-  bool flat = false;
+  int ngen = 0, myk = 0, G = 1, TW = 0, TC = 0;
   uint32_t ar[NARROW_ONLY ? 1 : kFlatR];
   float fr[NARROW_ONLY ? 1 : kFlatR];
   int kr[NARROW_ONLY ? 1 : kFlatR];
@@ -457,17 +430,20 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
       T.lam[myk] = ly.lam0;
       T.m0[myk] = T.m1[myk] = ord_of(INFINITY);
     }
-    mode = int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
-    flat = mode == int(kFlat) && TW <= kFlatCap && TC <= kFlatCap;
     G = mode == int(kFlat) ? 64 : (1 << mode);
     __syncthreads();
     if (flat) {
       // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
-      // t = s + r * kTile; slots past the tile's nodes are skipped per wavefront. The layers of all
-      // the lane's nodes are found first, together.
+      // t = s + r * kTile, its layer's rank from the node maps in the stage; slots past the tile's
+      // nodes are skipped per wavefront.
+      const uint8_t *maps = reinterpret_cast<const uint8_t *>(s_cb);
       int ks[kFlatR], kcs[kFlatR];
-      slot_layers(T.wo, ngen, TW, s, ks);
-      slot_layers(T.co, ngen, TC, s, kcs);
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
+        const int t = s + r * kTile;
+        ks[r] = t < TW ? int(maps[t]) : 0;
+        kcs[r] = t < TC ? int(maps[TW + t]) : 0;
+      }
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         kr[r] = -1;
@@ -497,6 +473,8 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
           if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];
         }
       }
+      // every lane has read its ranks before the stage takes the backward messages
+      __syncthreads();
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r)
         if (kc[r] >= 0) s_cb[s + r * kTile] = cbr[r];

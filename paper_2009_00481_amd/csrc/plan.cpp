@@ -373,6 +373,47 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
       }
     }
   }
+  // node maps of the flat path: each tile's general layers in position order, their own nodes
+  // then their child nodes, each mapped to the layer's rank; only tiles within the flat stage; each
+  // tile's maps at a multiple of 16 bytes, padded to one
+  for (int pass = 0; pass < 2; ++pass) {
+    const auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;
+    const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+    const auto &gt = pass ? P.bgt : P.fgt;
+    const auto &gm = pass ? P.bgm : P.fgm;
+    if (gt.size() != tiles.size() || gm.size() % 16) return "node map records";
+    size_t used = 0;
+    for (const WaveRange &wr : waves)
+      for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+        const int64_t p0 = uint32_t(tiles[2 * size_t(t)]) & kTilePosMask;
+        const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+        std::vector<int32_t> own, chl;
+        int32_t k = 0;
+        for (int64_t q = p0; q < p1; ++q) {
+          const int64_t L = (pass && wr.list) ? P.bwd_list[size_t(q)] : q;
+          if (((P.meta[size_t(L)] >> kMetaWidthShift) & 3u) != 0u) continue;
+          own.insert(own.end(), size_t(ownw[size_t(L)]), k);
+          chl.insert(chl.end(), size_t(childw[size_t(L)]), k);
+          ++k;
+        }
+        const bool flat = k > 0 && own.size() <= size_t(kFlatCap) && chl.size() <= size_t(kFlatCap);
+        const int32_t off = gt[2 * size_t(t)], sizes = gt[2 * size_t(t) + 1];
+        if (!flat) {
+          if (off != -1) return "node map of a tile outside the flat stage";
+          continue;
+        }
+        const size_t len = (own.size() + chl.size() + 15) / 16 * 16;
+        if (off < 0 || off % 16 || size_t(off) != used || sizes != int32_t(own.size() | (chl.size() << 16)) ||
+            size_t(off) + len > gm.size())
+          return "node map record";
+        for (size_t q = 0; q < own.size(); ++q)
+          if (gm[size_t(off) + q] != own[q]) return "own node map";
+        for (size_t q = 0; q < chl.size(); ++q)
+          if (gm[size_t(off) + own.size() + q] != chl[q]) return "child node map";
+        used += len;
+      }
+    if (used != gm.size()) return "node map size";
+  }
   for (int32_t j = 0; j < P.m; ++j)
     if (P.root_slot[j] >= S || P.bdd_canon_off[j + 1] < P.bdd_canon_off[j]) return "roots";
   for (int32_t i = 0; i < P.n; ++i)
@@ -1054,6 +1095,41 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       }
   }
 
+  // node maps of the flat path: the layer rank of every own and child node a tile stages, so that
+  // the kernel reads it from LDS instead of searching the level offsets
+  for (int pass = 0; pass < 2; ++pass) {
+    const auto &tiles = pass ? P.bwd_tiles : P.fwd_tiles;
+    const auto &waves = pass ? P.bwd_waves : P.fwd_waves;
+    auto &gt = pass ? P.bgt : P.fgt;
+    auto &gm = pass ? P.bgm : P.fgm;
+    gt.assign(tiles.size(), 0);
+    gm.clear();
+    std::vector<int64_t> gen;
+    for (const WaveRange &wr : waves)
+      for (int32_t t = wr.tile_begin; t < wr.tile_end; ++t) {
+        gt[2 * size_t(t)] = -1;
+        gen.clear();
+        const int64_t p0 = uint32_t(tiles[2 * size_t(t)]) & kTilePosMask;
+        const int64_t p1 = uint32_t(tiles[2 * size_t(t) + 1]) & ~kTileRootBit;
+        int64_t tw = 0, tc = 0;
+        for (int64_t q = p0; q < p1; ++q) {
+          const int64_t Lq = (pass && wr.list) ? P.bwd_list[size_t(q)] : q;
+          if (((P.meta[size_t(Lq)] >> kMetaWidthShift) & 3u) != 0u) continue;
+          gen.push_back(Lq);
+          tw += ownw[size_t(Lq)];
+          tc += childw[size_t(Lq)];
+        }
+        if (gen.empty() || tw > kFlatCap || tc > kFlatCap) continue;
+        gt[2 * size_t(t)] = int32_t(gm.size());
+        gt[2 * size_t(t) + 1] = int32_t(tw | (tc << 16));
+        for (int part = 0; part < 2; ++part)
+          for (size_t k = 0; k < gen.size(); ++k)
+            gm.insert(gm.end(), size_t(part ? childw[size_t(gen[k])] : ownw[size_t(gen[k])]), uint8_t(k));
+        gm.resize((gm.size() + 15) / 16 * 16, 0);
+      }
+    if (gm.size() >= size_t(INT32_MAX)) return set_error(BDDMP_BDD_TOO_LARGE, "node maps beyond 2^31 bytes");
+  }
+
   // dataflow launch: each tile waits only for the tiles that write what it reads. In the forward
   // pass a layer reads its own level's forward messages, pushed by its parent layer; in the
   // backward pass its child level's backward messages, written by its child layer's backward step.
@@ -1278,6 +1354,10 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
   A.fqtile = take(4 * P.fqtile.size());
   A.bqptr = take(4 * P.bqptr.size());
   A.bqtile = take(4 * P.bqtile.size());
+  A.fgt = take(4 * P.fgt.size());
+  A.bgt = take(4 * P.bgt.size());
+  A.fgm = take(P.fgm.size() + 16);
+  A.bgm = take(P.bgm.size() + 16);
   A.fflag = take(4 * P.ftinfo.size());
   A.bflag = take(4 * P.btinfo.size());
   A.pctl = take(4 * 2 * size_t(kPassCtlWords));

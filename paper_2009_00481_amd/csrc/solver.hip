@@ -406,6 +406,10 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
   D.inst_cut = reinterpret_cast<const int32_t *>(b + A.inst_cut);
   D.inst_cut_idx = reinterpret_cast<const int32_t *>(b + A.inst_cut_idx);
   D.exit_rec = P.exit_rec.empty() ? nullptr : reinterpret_cast<const int32_t *>(b + A.exit_rec);
+  D.fgt = reinterpret_cast<const int2 *>(b + A.fgt);
+  D.bgt = reinterpret_cast<const int2 *>(b + A.bgt);
+  D.fgm = reinterpret_cast<const uint8_t *>(b + A.fgm);
+  D.bgm = reinterpret_cast<const uint8_t *>(b + A.bgm);
   D.gamma = P.split_gamma;
   for (int p = 0; p < 2; ++p) {
     PassArgs &pa = S->pass[p];
@@ -465,6 +469,10 @@ int32_t solver_bind(const Plan &P, void *arena, size_t bytes, void *stream, Solv
       up(A.fqtile, P.fqtile.data(), 4 * P.fqtile.size()),
       up(A.bqptr, P.bqptr.data(), 4 * P.bqptr.size()),
       up(A.bqtile, P.bqtile.data(), 4 * P.bqtile.size()),
+      up(A.fgt, P.fgt.data(), 4 * P.fgt.size()),
+      up(A.bgt, P.bgt.data(), 4 * P.bgt.size()),
+      up(A.fgm, P.fgm.data(), P.fgm.size()),
+      up(A.bgm, P.bgm.data(), P.bgm.size()),
   };
   for (hipError_t e : errs)
     if (e != hipSuccess) {

@@ -116,3 +116,34 @@ def test_wave_groups_wait_bound_reports_device_error(monkeypatch):
     assert np.array_equal(s.get_lambda().cpu().numpy(), ref.get_lambda().cpu().numpy())
     assert s.lower_bound()[0] == ref.lower_bound()[0]
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["no_rows", "degenerate_rows", "one_row", "one_variable"])
+def test_launch_forms_on_degenerate_plans(case):
+    """Plans with no rows, with empty and single-level rows and a variable in no row, with one row,
+    and with one variable: every launch form (waves, dataflow, two-branch, wave groups, and latest
+    waves) runs and gives the wave launches' multipliers and bounds bitwise."""
+    import torch
+
+    ilps = {
+        "no_rows": lambda: I.from_rows(4, np.array([1.0, -2.0, 0.5, -0.25]), []),
+        "degenerate_rows": lambda: I.from_rows(
+            5, np.array([-1.0, -0.5, 0.75, 0.25, -3.0]),
+            [([], [], 1, 0), ([0, 1], [1, 1], 1, 1), ([2], [1], 1, 0), ([3], [2], 2, 1), ([1, 3], [1, -1], 1, 0)]),
+        "one_row": lambda: I.from_rows(3, np.array([0.5, -1.0, 0.25]), [([0, 1, 2], [1, 1, 1], 0, 1)]),
+        "one_variable": lambda: I.from_rows(1, np.array([-0.5]), [([0], [1], 1, 1)]),
+    }
+    ilp = ilps[case]()
+    res = []
+    for align, mode, g in ((0, 0, 0), (0, 1, 1), (0, 2, 0), (0, 3, 2), (1, 3, 8), (1, 0, 0)):
+        plan = B.Plan(B.Problem.from_ilp(ilp), wave_align=align)
+        s = B.Solver(plan)
+        if mode:
+            s.set_launch(mode, g)
+        for graphs in (True, False):
+            s.set_graphs(graphs)
+            s.iterate(3)
+        res.append((s.get_lambda().cpu().numpy(), s.lb_history(7), s.lower_bound()[0]))
+        torch.cuda.synchronize()
+    for lam, hist, lb in res[1:]:
+        assert np.array_equal(lam, res[0][0]) and np.array_equal(hist, res[0][1]) and lb == res[0][2], case

@@ -57,6 +57,27 @@ struct Layer {
     return NARROW_ONLY || ((meta >> kMetaWidthShift) & 3u) != 0u;
   }
 
+  // begin() in two steps, for launches whose tiles wait for other tiles of the same pass: first the
+  // loads no tile of this pass writes (meta word, multiplier, neighbour layer, the other pass's
+  // message pair), then, once the tiles it depends on are done, the pair this pass writes (the own
+  // level's forward messages in a forward pass, the child level's backward messages in a backward
+  // pass) and the narrow min-marginals
+  __device__ __forceinline__ void begin_fixed(const Dev &D, int L_) {
+    L = L_;
+    meta = D.meta[L];
+    lam0 = D.lam[L];
+    tgt = DIR == kFwd ? D.child[L] : D.parent[L];
+    if (DIR == kFwd) b = msg_ld2<false>(D.mbc + 2 * L);
+    else f = msg_ld2<false>(D.mf + 2 * L);
+  }
+  __device__ __forceinline__ void begin_pass(const Dev &D) {
+    if (DIR == kFwd) f = msg_ld2<COH>(D.mf + 2 * L);
+    else b = msg_ld2<COH>(D.mbc + 2 * L);
+    m0 = INFINITY;
+    m1 = INFINITY;
+    if (narrow()) narrow_marginals(lam0);
+  }
+
   __device__ __forceinline__ void begin(const Dev &D, int L_) {
     L = L_;
     meta = D.meta[L];
@@ -314,9 +335,20 @@ struct WaveLds {
 // list: with LIST, whether this tile's positions go through bwd_list (callers that decide per tile
 // instantiate LIST true and pass the tile's flag; the wave launches leave it true).
 // COH: messages of this pass are read and written coherently (dataflow launch; see msg_ld).
-template <int DIR, int MODE, bool NARROW_ONLY, bool LIST, bool COH = false>
+// No wait inside a tile (wave launches, and tiles whose launch waited before the tile).
+struct NoWait {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <int DIR, int MODE, bool NARROW_ONLY, bool LIST, bool COH = false, class Wait = NoWait>
 __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh, const int tix, const int btix,
-                                          const uint32_t w0, const uint32_t end, const bool list = true) {
+                                          const uint32_t w0, const uint32_t end, const bool list = true,
+                                          const Wait &wait = Wait{}) {
+  // with a wait (a tile of a launch that also runs the tiles it depends on), the loads no tile of
+  // this pass writes (and, in general tiles, the width scan) come first, then the wait, then the
+  // messages this pass writes
+  constexpr bool kDeferred = !std::is_same_v<Wait, NoWait>;
+  static_assert(!kDeferred || MODE == kUpdate, "deferred waits: update mode");
   float *const s_d = sh.d;
   int *const s_wcnt = sh.wcnt;
   auto &s_g = sh.g;
@@ -364,7 +396,12 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
       grec = D.grec[L];
       gnb = D.gnb[L];
     }
-    ly.begin(D, L);
+    if constexpr (kDeferred) ly.begin_fixed(D, L);
+    else ly.begin(D, L);
+  }
+  if constexpr (kDeferred && NARROW_ONLY) {
+    wait();
+    if (active) ly.begin_pass(D);
   }
   // the maps into the stage (free until the staging below; the width scan's barriers publish them)
   if constexpr (!NARROW_ONLY)
@@ -432,6 +469,10 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
     }
     G = mode == int(kFlat) ? 64 : (1 << mode);
     __syncthreads();
+    if constexpr (kDeferred) {
+      wait();
+      if (active) ly.begin_pass(D);
+    }
     if (flat) {
       // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
       // t = s + r * kTile, its layer's rank from the node maps in the stage; slots past the tile's
@@ -730,6 +771,19 @@ __device__ __forceinline__ void wait_deps(const int4 ra, const int4 rb, const in
   __syncthreads();
 }
 
+// wait_deps for one tile as a callable (on: whether the tile waits at all)
+struct DepWait {
+  int4 ra, rb;
+  const int32_t *dep_list;
+  const uint32_t *flags;
+  uint32_t gen, spin_limit;
+  uint32_t *err;
+  bool on;
+  __device__ __forceinline__ void operator()() const {
+    if (on) wait_deps(ra, rb, dep_list, flags, gen, spin_limit, err);
+  }
+};
+
 template <int DIR, bool NARROW_PLAN>
 __global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(NARROW_PLAN ? 8 : 6)))
 void pass_kernel(const Dev D, const PassArgs A) {
@@ -766,15 +820,15 @@ void pass_kernel(const Dev D, const PassArgs A) {
       const int t = A.qtile[q0 + j];
       const int4 ra = A.trec[2 * t], rb = A.trec[2 * t + 1];
       const uint32_t info = uint32_t(ra.z);
-      wait_deps(ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr);
       const bool list = (info & 2u) != 0u;
       set_priority((info >> 2) & 3u);
+      const DepWait dw{ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr, true};
       if constexpr (NARROW_PLAN) {
-        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
       } else if (info & 1u) {
-        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+        wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
       } else {
-        wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+        wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
       }
       // every lane's coherent message stores of the tile complete (vmcnt 0; expcnt and lgkmcnt at
       // their maximum) before one lane stores the tile's flag; the barrier also frees the LDS
@@ -829,14 +883,15 @@ void group_kernel(const Dev D, const GroupArgs A) {
   const uint32_t gen = uint32_t(*D.hist_n) | 0x80000000u;
   const int4 ra = A.trec[2 * t], rb = A.trec[2 * t + 1];
   const uint32_t info = uint32_t(ra.z);
-  if (i > 0) wait_deps(ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr);
   const bool list = (info & 2u) != 0u;
+  // the tile issues what no tile of this pass writes (and scans its widths) before it waits
+  const DepWait dw{ra, rb, A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr, i > 0};
   if constexpr (NARROW_PLAN) {
-    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
   } else if (info & 1u) {
-    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+    wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh.n, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
   } else {
-    wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list);
+    wave_tile<DIR, kUpdate, false, DIR == kBwd, true>(D, sh.g, t, t, uint32_t(ra.x), uint32_t(ra.y), list, dw);
   }
   if (i + 1 < A.nw) {
     __builtin_amdgcn_s_waitcnt(0x0F70);

@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--only", choices=["batched", "smoothed", "split"], default=None,
                     help="run only this comparison and print its object (profiling)")
     ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--launch-probe-iters", type=int, default=50,
+                    help="iterations timed per launch form before the main workload's run")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--batch-group-waves", type=int, default=256,
                     help="consecutive waves per wave-group launch in the batched leg (1..256)")
@@ -433,6 +435,23 @@ def main():
     torch.cuda.synchronize()
     bind_s = time.perf_counter() - t
 
+    # launch form: one launch per wave, or every wave of a pass in one wave-group launch (the same
+    # results bitwise); the faster on a short burst of iterations is kept
+    forms = {"waves": (0, 0, "wave_kernel", ""), "wave_groups": (3, 4096, "group_kernel", "group_")}
+    form_ms = {}
+    for name, (mode, chunk, _, _) in forms.items():
+        s.set_launch(mode, chunk)
+        s.iterate(3)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.iterate(args.launch_probe_iters)
+        torch.cuda.synchronize()
+        form_ms[name] = (time.perf_counter() - t) * 1e3 / args.launch_probe_iters
+    launch = min(form_ms, key=form_ms.get)
+    mode, chunk, kname, tprefix = forms[launch]
+    s.set_launch(mode, chunk)
+    log(f"[bench] launch forms (ms per iteration): {form_ms}; using {launch}")
+
     I_ = int(st.n_incidences)
     m0 = torch.empty(max(I_, 1), dtype=torch.float32, device="cuda")
     m1 = torch.empty_like(m0)
@@ -470,7 +489,7 @@ def main():
     iter_ms = kt["iter_ms"]
     gbps_iter = iter_bytes / (iter_ms * 1e-3) / 1e9 if iter_ms > 0 else None
 
-    roofline = roofline_of(kt, committed_traffic(args.workload))
+    roofline = roofline_of(kt, committed_traffic(args.workload, tprefix), kname)
 
     # time to bound: first t with LB_t >= LB* - 1e-4 max(|LB*|, 1). LB* is the fp64 oracle's LB_T on
     # the same instance when it is stored for T iterations, else this run's own LB_T. Measured with
@@ -563,7 +582,10 @@ def main():
         "config": {"workload": args.workload, "iterations_per_step": T, "n_vars": int(st.n_vars),
                    "n_bdds": int(st.n_bdds), "n_nodes": int(st.n_nodes), "n_incidences": int(st.n_incidences),
                    "n_arcs_live": int(st.n_arcs_live), "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
-                   "bound_dtype": "f64"},
+                   "bound_dtype": "f64",
+                   "launch": {"waves": "one launch per wave (launch mode 0)",
+                              "wave_groups": "every wave of a pass in one wave-group launch (launch mode 3)"}[launch]},
+        "launch_probe_ms_per_iter": form_ms,
         "hbm_gbps_per_iter": gbps_iter, "iter_ms": iter_ms, "model_bytes_per_iter": iter_bytes,
         "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit,
         "time_to_bound_from_iter_ms": None if t_hit is None else t_hit * iter_ms,

@@ -441,15 +441,15 @@ int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
  * wave's last workgroups overlap the next wave's first ones. The turnaround and wrap-around fusions
  * are not used; results are bitwise those of mode 0. chunk is ignored by modes 0 and 2.
  * mode 3 (wave groups; plans with bddmp_stats.dataflow = 1): chunk consecutive waves of a pass per
- * launch (0: 4; at most 256), one workgroup per tile. Each wave's workgroups form one block range
- * in wave order; a tile of a later wave of the launch first waits for the flags of the tiles it
- * reads from (dependency lists as in mode 1), whose messages are written and read coherently, so
- * the tiles of consecutive waves overlap instead of meeting at a launch boundary. Progress rests on
- * each XCD dispatching its workgroups in block order (every earlier wave's workgroups are
- * dispatched before a later wave's); each wait is bounded all the same, with the error path of
- * mode 1 (about a quarter of a second per wait). The turnaround and wrap-around fusions are not
- * used; results are bitwise those of mode 0. get: chunk is the waves per launch.
- * INVALID_ARG for modes 1-3 on a plan without dataflow support, or chunk above 256 in mode 3.
+ * launch (0: 4), one workgroup per tile in pass order. A tile of a later wave of the launch first
+ * waits for the flags of the tiles it reads from (dependency lists as in mode 1), whose messages
+ * are written and read coherently, so the tiles of consecutive waves overlap instead of meeting at
+ * a launch boundary. Progress rests on each XCD dispatching its workgroups in block order (every
+ * earlier wave's workgroups are dispatched before a later wave's); each wait is bounded all the
+ * same, with the error path of mode 1 (about a quarter of a second per wait). The turnaround and
+ * wrap-around fusions are not used; results are bitwise those of mode 0. get: chunk is the waves
+ * per launch.
+ * INVALID_ARG for modes 1-3 on a plan without dataflow support.
  * get: either pointer may be NULL.
  * For tests of that failure path, the environment variable BDDMP_PASS_SPIN_LIMIT (read by this
  * call) replaces the bound: the polls of one wait before it gives up.

@@ -92,20 +92,18 @@ hipError_t launch_pass(int dir, bool narrow_plan, int grid, const Dev &D, const 
 // Resident workgroups per CU of the pass kernel (the launch's grid is this times the CU count).
 hipError_t pass_blocks_per_cu(int dir, bool narrow_plan, int *blocks);
 
-// Several consecutive waves of one update pass in one launch (launch mode 3): wave i of the launch
-// holds the pass's tiles [tofs[i], tofs[i+1]) and the workgroups [wofs[i], wofs[i+1]) (multiples of
-// 8; a wave's workgroups beyond its tiles exit at once). A tile of wave i > 0 waits for the flags of
-// the tiles it reads from; every tile stores its flag. The flag value is the bound counter with bit
-// 31 set, the same for both passes of an iteration and new in the next.
-constexpr int kGroupMaxWaves = 256;
+// Several consecutive waves of one update pass in one launch (launch mode 3): the pass's tiles
+// [t0, t_end), workgroup b running tile t0 + b; [t0, t_first) is the launch's first wave and
+// [t_last, t_end) its last. A tile past the first wave waits for the flags of the tiles it reads
+// from; every tile stores its flag. The flag value is the bound counter with bit 31 set, the same
+// for both passes of an iteration and new in the next.
 struct GroupArgs {
   const int4 *trec;      // as PassArgs
   const int32_t *dep_list;
   uint32_t *flags;
   uint32_t *ctl;         // the pass's control words (error word)
   uint32_t spin_limit;
-  int32_t nw;
-  int32_t tofs[kGroupMaxWaves + 1], wofs[kGroupMaxWaves + 1];
+  int32_t t0, t_first, t_last, t_end;
 };
 hipError_t launch_group(int dir, bool narrow_plan, const Dev &D, const GroupArgs &A, hipStream_t s);
 

@@ -194,26 +194,23 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
     return tm.stop(st, S.pass[p].n_tiles > 0 ? 1 : 0);
   }
   if (S.group_waves && mode == kUpdate) {
-    // group_waves consecutive waves per launch, each wave's workgroups rounded up to a multiple of 8
+    // group_waves consecutive waves per launch, one workgroup per tile
     const int p = dir == kFwd ? 0 : 1;
     int launches = 0;
     for (size_t w = 0; w < waves.size(); w += size_t(S.group_waves)) {
+      const size_t wl = std::min(waves.size(), w + size_t(S.group_waves)) - 1;
       GroupArgs ga{};
       ga.trec = S.pass[p].trec;
       ga.dep_list = S.pass[p].dep_list;
       ga.flags = S.pass[p].flags;
       ga.ctl = S.pass[p].ctl;
       ga.spin_limit = S.group_spin;
-      ga.nw = int32_t(std::min(waves.size() - w, size_t(S.group_waves)));
-      ga.tofs[0] = waves[w].tile_begin;
-      ga.wofs[0] = 0;
-      for (int i = 0; i < ga.nw; ++i) {
-        const WaveRange &wr = waves[w + size_t(i)];
-        ga.tofs[i + 1] = wr.tile_end;
-        ga.wofs[i + 1] = ga.wofs[i] + (wr.tile_end - wr.tile_begin + 7) / 8 * 8;
-      }
+      ga.t0 = waves[w].tile_begin;
+      ga.t_first = waves[w].tile_end;
+      ga.t_last = waves[wl].tile_begin;
+      ga.t_end = waves[wl].tile_end;
       if (int32_t rc = launched(launch_group(dir, P.n_general == 0, S.D, ga, st), "wave-group kernel")) return rc;
-      launches += ga.wofs[ga.nw] > 0 ? 1 : 0;
+      launches += ga.t_end > ga.t0 ? 1 : 0;
     }
     return tm.stop(st, launches);
   }
@@ -687,8 +684,6 @@ int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
     return set_error(BDDMP_INVALID_ARG,
                      "launch mode must be 0 (wave launches), 1 (dataflow), 2 (two-branch waves) or 3 (wave groups)");
   if (chunk < 0 || chunk > 4096) return set_error(BDDMP_INVALID_ARG, "chunk must be 0 (default) .. 4096");
-  if (mode == 3 && chunk > kGroupMaxWaves)
-    return set_error(BDDMP_INVALID_ARG, "waves per wave-group launch must be 0 (default) .. " + std::to_string(kGroupMaxWaves));
   if (mode != 0 && !P.pers_ok)
     return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow or two-branch launch");
   if (mode == 2) {

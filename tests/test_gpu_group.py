@@ -47,13 +47,14 @@ def test_wave_groups_split_plan_bitwise():
 
 
 def test_wave_groups_full_size_mrf_bitwise():
-    """The 256x256x8 Potts benchmark workload with 2, 4 and 8 waves per launch: multipliers and
-    bounds after 3 iterations bitwise those of the wave launches."""
+    """The 256x256x8 Potts benchmark workload with 2, 4 and 8 waves per launch and with every wave of
+    a pass in one launch: multipliers and bounds after 3 iterations bitwise those of the wave
+    launches."""
     import torch
 
     plan = B.Plan(B.Problem.from_ilp(I.config(2)))
     res = []
-    for mode, g in ((0, 0), (3, 2), (3, 4), (3, 8)):
+    for mode, g in ((0, 0), (3, 2), (3, 4), (3, 8), (3, 4096)):
         print(f"[wave groups full] mode {mode} waves {g}", flush=True)
         s = B.Solver(plan)
         s.set_launch(mode, g)
@@ -81,7 +82,7 @@ def test_wave_groups_switching_and_arguments():
         assert np.array_equal(a.get_lambda().cpu().numpy(), b.get_lambda().cpu().numpy()), (mode, g)
     assert np.array_equal(a.lb_history(19), b.lb_history(19))
     with pytest.raises(B.BddmpError) as e:
-        b.set_launch(3, 257)
+        b.set_launch(3, 4097)
     assert e.value.code == -1
     torch.cuda.synchronize()
 

@@ -3,8 +3,8 @@ of a pass per launch, one workgroup per tile, a later wave's tiles waiting only 
 the tiles they read from. Each tile runs the same operations as with one launch per wave, after
 every tile it reads from, so every output must be bitwise equal to the wave launches: multipliers,
 bounds, min-marginals, rounded primal, per-instance bounds; with graph replay and eager launches;
-narrow, wide, list, batched and split plans; 2, 3 and 8 waves per launch; switching launch forms
-between calls. A wait that exceeds its bound is forced from the host (a spin limit of zero) and
+narrow, wide, list, batched and split plans; 2, 3 and 8 waves per launch and every wave of a pass
+in one launch; switching launch forms between calls. A wait that exceeds its bound is forced from the host (a spin limit of zero) and
 must come back as DEVICE from the next bound read, every kernel exiting normally."""
 import numpy as np
 import pytest
@@ -22,7 +22,7 @@ def test_wave_groups_equal_wave_launches_bitwise(name):
     T = 4
     print(f"[wave groups] {name}", flush=True)
     plan, ref = _run(insts, 0, 0, True, T)
-    for graphs, g in ((True, 2), (True, 3), (False, 8)):
+    for graphs, g in ((True, 2), (True, 3), (False, 8), (True, 4096)):
         _, got = _run(insts, 3, g, graphs, T)
         _same(ref, got, (name, graphs, g))
 
@@ -33,7 +33,7 @@ def test_latest_waves_equal_earliest_waves_bitwise():
     bounds, min-marginals, rounded primal and instance bounds."""
     insts = _cases()["batch"]()
     _, ref = _run(insts, 0, 0, True, 4)
-    for mode, g in ((0, 0), (3, 4), (3, 256)):
+    for mode, g in ((0, 0), (3, 4), (3, 256), (3, 4096)):
         _, got = _run(insts, mode, g, True, 4, wave_align=1)
         _same(ref, got, ("latest waves", mode, g))
 

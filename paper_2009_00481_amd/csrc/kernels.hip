@@ -383,8 +383,12 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
   // levels fit the stage): the tile's node maps, 16 bytes per lane, loaded with the layer records
   const int mode = NARROW_ONLY ? 0 : int((D.gsel >> (4 * (w0 >> kTileClsShift))) & 0xFu);
   int2 gtr = make_int2(-1, 0);
-  if constexpr (!NARROW_ONLY)
-    if (mode == int(kFlat)) gtr = (DIR == kFwd ? D.fgt : D.bgt)[tix];
+  if constexpr (!NARROW_ONLY) {
+    // every tile has a map record, so it is read whatever the width class, in flight together with
+    // the caller's read of the tile's start and end words rather than after it
+    gtr = (DIR == kFwd ? D.fgt : D.bgt)[tix];
+    if (mode != int(kFlat)) gtr.x = -1;
+  }
   const bool flat = !NARROW_ONLY && gtr.x >= 0;
   const bool map_lane = flat && 16 * s < (gtr.y & 0xFFFF) + int(uint32_t(gtr.y) >> 16);
   uint4 gmp = make_uint4(0u, 0u, 0u, 0u);

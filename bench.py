@@ -64,8 +64,9 @@ def kernel_source_hash() -> str:
 
 def committed_traffic(workload: str, kernel: str = ""):
     """HBM bytes per launch of the update kernels (kernel "": one launch per wave; "group_": the
-    wave-group launch) from the committed counter summary, or None when the summary is missing,
-    lacks them or was taken on different kernel sources."""
+    wave-group launch; "pair_": the wave-group launch with two tiles per workgroup) from the
+    committed counter summary, or None when the summary is missing, lacks them or was taken on
+    different kernel sources."""
     path = os.path.join(ROOT, "profiles", f"wave_kernels_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -435,9 +436,13 @@ def main():
     torch.cuda.synchronize()
     bind_s = time.perf_counter() - t
 
-    # launch form: one launch per wave, or every wave of a pass in one wave-group launch (the same
-    # results bitwise); the faster on a short burst of iterations is kept
-    forms = {"waves": (0, 0, "wave_kernel", ""), "wave_groups": (3, 4096, "group_kernel", "group_")}
+    # launch form: one launch per wave, or every wave of a pass in one wave-group launch with one
+    # or (plans whose layers are all narrow) two tiles per workgroup (the same results bitwise); the
+    # fastest on a short burst of iterations is kept
+    forms = {"waves": (0, 0, "wave_kernel", ""), "wave_groups": (3, 4096, "group_kernel", "group_"),
+             "wave_group_pairs": (4, 4096, "group_pair_kernel", "pair_")}
+    if int(st.max_width) > 2:
+        del forms["wave_group_pairs"]
     form_ms = {}
     for name, (mode, chunk, _, _) in forms.items():
         s.set_launch(mode, chunk)
@@ -584,7 +589,9 @@ def main():
                    "n_arcs_live": int(st.n_arcs_live), "waves_per_pass": [int(st.waves_fwd), int(st.waves_bwd)],
                    "bound_dtype": "f64",
                    "launch": {"waves": "one launch per wave (launch mode 0)",
-                              "wave_groups": "every wave of a pass in one wave-group launch (launch mode 3)"}[launch]},
+                              "wave_groups": "every wave of a pass in one wave-group launch (launch mode 3)",
+                              "wave_group_pairs": "every wave of a pass in one wave-group launch, two tiles per "
+                                                  "workgroup (launch mode 4)"}[launch]},
         "launch_probe_ms_per_iter": form_ms,
         "hbm_gbps_per_iter": gbps_iter, "iter_ms": iter_ms, "model_bytes_per_iter": iter_bytes,
         "time_to_bound_1e-4_ms": ttb_ms, "time_to_bound_iters": t_hit,

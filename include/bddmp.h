@@ -449,7 +449,14 @@ int32_t bddmp_solver_set_graphs(bddmp_solver *s, int32_t enable);
  * same, with the error path of mode 1 (about a quarter of a second per wait). The turnaround and
  * wrap-around fusions are not used; results are bitwise those of mode 0. get: chunk is the waves
  * per launch.
- * INVALID_ARG for modes 1-3 on a plan without dataflow support.
+ * mode 4 (wave groups, two tiles per workgroup; plans with bddmp_stats.dataflow = 1 whose layers
+ * are all narrow, bddmp_stats.max_width <= 2): mode 3 with each workgroup taking two consecutive
+ * tiles of the pass order, both tiles' loads and waits issued together, so that twice the loads
+ * are in flight per workgroup; a pair whose second tile reads from its first (a pair across a wave
+ * boundary) runs them one after the other. It pays on waves of several thousand tiles (halving the
+ * workgroups leaves a GPU idle on small waves). Results are bitwise those of mode 0. INVALID_ARG
+ * on a plan with general layers.
+ * INVALID_ARG for modes 1-4 on a plan without dataflow support.
  * get: either pointer may be NULL.
  * For tests of that failure path, the environment variable BDDMP_PASS_SPIN_LIMIT (read by this
  * call) replaces the bound: the polls of one wait before it gives up.

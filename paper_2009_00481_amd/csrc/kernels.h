@@ -105,7 +105,8 @@ struct GroupArgs {
   uint32_t spin_limit;
   int32_t t0, t_first, t_last, t_end;
 };
-hipError_t launch_group(int dir, bool narrow_plan, const Dev &D, const GroupArgs &A, hipStream_t s);
+// pairs: two tiles per workgroup (group_pair_kernel; plans whose layers are all narrow)
+hipError_t launch_group(int dir, bool narrow_plan, bool pairs, const Dev &D, const GroupArgs &A, hipStream_t s);
 
 // Big tiles (one variable with more than kTile rows each) of one wave.
 hipError_t launch_wave_big(int dir, int mode, bool list, int nb, int big0, const Dev &D, hipStream_t s);

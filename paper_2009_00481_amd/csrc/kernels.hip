@@ -753,25 +753,31 @@ __device__ __forceinline__ void set_priority(uint32_t p) {
 // lanes poll them with coherent loads, each at most spin_limit times (past it the error word is set
 // and the wait ends); then the workgroup's barrier, after which its lanes read the messages with
 // coherent loads (no cache holds a stale copy for them to hit).
+// one wavefront polls a tile's dependencies (lane: its lane index): each lane waits for every 64th
+// flag until it holds gen, or sets the error word past spin_limit polls of one flag
+__device__ __forceinline__ void poll_deps(const int4 ra, const int4 rb, const int32_t *dep_list, const uint32_t *flags,
+                                          uint32_t gen, uint32_t spin_limit, uint32_t *err, int lane) {
+  const int nd = int((uint32_t(ra.z) >> 8) & 0x1FFu);
+  for (int e = lane; e < nd; e += 64) {
+    const int u = nd <= 4 ? (e == 0 ? rb.x : (e == 1 ? rb.y : (e == 2 ? rb.z : rb.w))) : dep_list[ra.w + e];
+    const uint32_t *f = flags + u;
+    uint32_t spins = 0u;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+      if (++spins > spin_limit) {
+        atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
 __device__ __forceinline__ void wait_deps(const int4 ra, const int4 rb, const int32_t *dep_list, const uint32_t *flags,
                                           uint32_t gen, uint32_t spin_limit, uint32_t *err) {
   const int nd = int((uint32_t(ra.z) >> 8) & 0x1FFu);
   if (!nd) return;
   const int s = int(threadIdx.x);
-  if (s < 64) {
-    for (int e = s; e < nd; e += 64) {
-      const int u = nd <= 4 ? (e == 0 ? rb.x : (e == 1 ? rb.y : (e == 2 ? rb.z : rb.w))) : dep_list[ra.w + e];
-      const uint32_t *f = flags + u;
-      uint32_t spins = 0u;
-      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
-        if (++spins > spin_limit) {
-          atomicOr(err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-  }
+  if (s < 64) poll_deps(ra, rb, dep_list, flags, gen, spin_limit, err, s);
   __syncthreads();
 }
 
@@ -898,6 +904,137 @@ void group_kernel(const Dev D, const GroupArgs A) {
     __syncthreads();
   }
   if (s == 0) __hip_atomic_store(A.flags + t, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-group launch of a plan whose layers are all narrow, two tiles per workgroup: tiles
+// a = t0 + 2 * block and a + 1 (when inside the launch), lane s holding layer s of both, so that
+// both tiles' fixed loads, dependency polls and message loads are in flight together and a
+// workgroup keeps twice the loads of the one-tile form outstanding. Each layer's arithmetic is that
+// of the one-tile form (the same J_i sum order, update, forward push or backward step, bound
+// partials per tile and wavefront), so the results are bitwise the same.
+//
+// When tile a + 1 reads messages tile a writes (the two lie in consecutive waves, and a is then the
+// last of its ascending dependency list), the workgroup runs tile a, publishes it, then runs tile
+// a + 1, each in the one-tile form. Progress as for group_kernel: the workgroups take the pairs in
+// pass order, and a pair waits only for tiles of earlier pairs, or for its own first tile once that
+// tile is published.
+template <int DIR>
+__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(8)))
+void group_pair_kernel(const Dev D, const GroupArgs A) {
+  __shared__ WaveLds<true> sh;
+  __shared__ float p_d[2][kTile], p_share[2][kTile];
+  __shared__ int p_nf[2][kTile];
+  const int s = int(threadIdx.x);
+  const int ta = A.t0 + 2 * int(blockIdx.x);
+  const bool two = ta + 1 < A.t_end;
+  const int tb = two ? ta + 1 : ta;
+  const uint32_t gen = uint32_t(*D.hist_n) | 0x80000000u;
+  const int4 ra[2] = {A.trec[2 * ta], A.trec[2 * tb]};
+  const int4 rb[2] = {A.trec[2 * ta + 1], A.trec[2 * tb + 1]};
+  const int ndb = int((uint32_t(ra[1].z) >> 8) & 0x1FFu);
+  int last_b = -1;
+  if (two && tb >= A.t_first && ndb > 0)
+    last_b = ndb <= 4 ? (ndb == 1 ? rb[1].x : (ndb == 2 ? rb[1].y : (ndb == 3 ? rb[1].z : rb[1].w)))
+                      : A.dep_list[ra[1].w + ndb - 1];
+  if (last_b == ta) {
+    // tile a + 1 waits for tile a: one after the other (tile a lies before the launch's last wave,
+    // so its publication below ends with the barrier that also frees the LDS for tile a + 1)
+    for (int k = 0; k < 2; ++k) {
+      const int t = ta + k;
+      const DepWait dw{ra[k], rb[k], A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr, t >= A.t_first};
+      wave_tile<DIR, kUpdate, true, DIR == kBwd, true>(D, sh, t, t, uint32_t(ra[k].x), uint32_t(ra[k].y),
+                                                       (uint32_t(ra[k].z) & 2u) != 0u, dw);
+      if (t < A.t_last) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+      }
+      if (s == 0) __hip_atomic_store(A.flags + t, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  Layer<DIR, true, false, true> ly[2];
+  bool act[2], roots[2];
+  int lay[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t w0 = uint32_t(ra[k].x), end = uint32_t(ra[k].y);
+    const int p0 = int(w0 & kTilePosMask);
+    const bool real = k == 0 || two;
+    roots[k] = real && DIR == kBwd && (end & kTileRootBit) != 0u;
+    act[k] = real && s < int(end & ~kTileRootBit) - p0;
+    // every lane loads (a lane past the tile's layers reads its first one and keeps nothing), so
+    // no branch separates the two tiles' loads
+    const int q = p0 + (act[k] ? s : 0);
+    const bool list = (uint32_t(ra[k].z) & 2u) != 0u;
+    lay[k] = (DIR == kBwd && list) ? D.bwd_list[q] : q;
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) ly[k].begin_fixed(D, lay[k]);
+  // wavefront 0 polls tile a's dependencies, wavefront 1 tile a + 1's, then one barrier
+  {
+    const int k = s >> 6;
+    if (k < 2 && (k == 0 || two) && ta + k >= A.t_first)
+      poll_deps(k ? ra[1] : ra[0], k ? rb[1] : rb[0], A.dep_list, A.flags, gen, A.spin_limit, A.ctl + kPassErr, s & 63);
+    __syncthreads();
+  }
+  // both tiles' messages of this pass in flight together, then their min-marginals
+  float2 pm[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) pm[k] = msg_ld2<true>((DIR == kFwd ? D.mf : D.mbc) + 2 * ly[k].L);
+  float d[2], lam1[2];
+  int pos[2], len[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (DIR == kFwd) ly[k].f = pm[k];
+    else ly[k].b = pm[k];
+    ly[k].narrow_marginals(ly[k].lam0);
+    d[k] = act[k] ? ly[k].m1 - ly[k].m0 : 0.0f;
+    lam1[k] = ly[k].lam0;
+    pos[k] = int((ly[k].meta >> kMetaPosShift) & kMetaField);
+    len[k] = int((ly[k].meta >> kMetaLenShift) & kMetaField);
+    p_d[k][s] = d[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (act[k] && pos[k] == 0) {
+      // J_i sum in ascending row order (the segment is sorted by row)
+      float sum = 0.0f;
+      int nf = 0;
+      for (int q = 0; q < len[k]; ++q) {
+        const float dq = p_d[k][s + q];
+        if (isinf(dq)) ++nf;
+        else sum += dq;
+      }
+      p_share[k][s] = nf ? sum / float(nf) : sum / float(len[k]);
+      p_nf[k][s] = nf;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (act[k]) {
+      const int h = s - pos[k];
+      lam1[k] = updated(lam1[k], d[k], p_share[k][h], p_nf[k][h]);
+      D.lam[ly[k].L] = lam1[k];
+    }
+    if (DIR == kFwd) {
+      if (act[k]) ly[k].push(D, lam1[k]);
+    } else {
+      const double e = act[k] ? ly[k].bstep(D, lam1[k]) : 0.0;
+      if (roots[k]) {
+        const double v = wave_sum(e);
+        if ((s & 63) == 0) D.lbpart[kTile / 64 * (ta + k) + (s >> 6)] = v;
+      }
+    }
+  }
+  if (ta < A.t_last) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+  }
+  if (s == 0) {
+    __hip_atomic_store(A.flags + ta, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (two) __hip_atomic_store(A.flags + tb, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // One variable with more than kTile rows per workgroup (its layers are the whole tile).
@@ -1241,11 +1378,20 @@ static hipError_t group_dispatch(const Dev &D, const GroupArgs &A, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_group(int dir, bool narrow_plan, const Dev &D, const GroupArgs &A, hipStream_t s) {
-  // t0 <= t_first <= t_end and t0 <= t_last <= t_end (t_last = t0 when the launch holds one wave)
-  if (A.t0 < 0 || A.t_first < A.t0 || A.t_end < A.t_first || A.t_last < A.t0 || A.t_end < A.t_last)
+template <int DIR>
+static hipError_t group_pair_dispatch(const Dev &D, const GroupArgs &A, hipStream_t s) {
+  hipLaunchKernelGGL((group_pair_kernel<DIR>), dim3((A.t_end - A.t0 + 1) / 2), dim3(kTile), 0, s, D, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_group(int dir, bool narrow_plan, bool pairs, const Dev &D, const GroupArgs &A, hipStream_t s) {
+  // t0 <= t_first <= t_end and t0 <= t_last <= t_end (t_last = t0 when the launch holds one wave);
+  // two tiles per workgroup only where every layer is narrow
+  if (A.t0 < 0 || A.t_first < A.t0 || A.t_end < A.t_first || A.t_last < A.t0 || A.t_end < A.t_last ||
+      (pairs && !narrow_plan))
     return hipErrorInvalidValue;
   if (A.t_end <= A.t0) return hipSuccess;
+  if (pairs) return dir == kFwd ? group_pair_dispatch<kFwd>(D, A, s) : group_pair_dispatch<kBwd>(D, A, s);
   if (dir == kFwd) return narrow_plan ? group_dispatch<kFwd, true>(D, A, s) : group_dispatch<kFwd, false>(D, A, s);
   return narrow_plan ? group_dispatch<kBwd, true>(D, A, s) : group_dispatch<kBwd, false>(D, A, s);
 }

@@ -49,8 +49,10 @@ struct Solver {
   bool pipe = false;
   hipStream_t side = nullptr, cap_side = nullptr;
   std::vector<hipEvent_t> pipe_ev;
-  // wave-group launches: waves per launch (0: off) and the bound of one dependency wait
+  // wave-group launches: waves per launch (0: off), two tiles per workgroup (plans whose layers
+  // are all narrow) and the bound of one dependency wait
   int group_waves = 0;
+  bool group_pairs = false;
   uint32_t group_spin = 0;
   ~Solver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -194,7 +196,7 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
     return tm.stop(st, S.pass[p].n_tiles > 0 ? 1 : 0);
   }
   if (S.group_waves && mode == kUpdate) {
-    // group_waves consecutive waves per launch, one workgroup per tile
+    // group_waves consecutive waves per launch, one workgroup per tile (per two tiles with group_pairs)
     const int p = dir == kFwd ? 0 : 1;
     int launches = 0;
     for (size_t w = 0; w < waves.size(); w += size_t(S.group_waves)) {
@@ -209,7 +211,8 @@ int32_t run_pass(Solver &S, int dir, int mode, std::vector<EventPair> *ev, hipSt
       ga.t_first = waves[w].tile_end;
       ga.t_last = waves[wl].tile_begin;
       ga.t_end = waves[wl].tile_end;
-      if (int32_t rc = launched(launch_group(dir, P.n_general == 0, S.D, ga, st), "wave-group kernel")) return rc;
+      if (int32_t rc = launched(launch_group(dir, P.n_general == 0, S.group_pairs, S.D, ga, st), "wave-group kernel"))
+        return rc;
       launches += ga.t_end > ga.t0 ? 1 : 0;
     }
     return tm.stop(st, launches);
@@ -680,12 +683,14 @@ int32_t solver_round_primal(Solver &S, float *M_dev, int8_t *x_host, double *obj
 
 int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
   const Plan &P = *S.plan;
-  if (mode < 0 || mode > 3)
-    return set_error(BDDMP_INVALID_ARG,
-                     "launch mode must be 0 (wave launches), 1 (dataflow), 2 (two-branch waves) or 3 (wave groups)");
+  if (mode < 0 || mode > 4)
+    return set_error(BDDMP_INVALID_ARG, "launch mode must be 0 (wave launches), 1 (dataflow), 2 (two-branch waves), "
+                                        "3 (wave groups) or 4 (wave groups, two tiles per workgroup)");
   if (chunk < 0 || chunk > 4096) return set_error(BDDMP_INVALID_ARG, "chunk must be 0 (default) .. 4096");
   if (mode != 0 && !P.pers_ok)
     return set_error(BDDMP_INVALID_ARG, "the plan has a variable in more than 256 rows: no dataflow or two-branch launch");
+  if (mode == 4 && P.n_general != 0)
+    return set_error(BDDMP_INVALID_ARG, "two tiles per workgroup (launch mode 4) need a plan whose layers are all narrow");
   if (mode == 2) {
     if (!S.side) HIP_TRY(hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     if (!S.cap_side) HIP_TRY(hipStreamCreateWithFlags(&S.cap_side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
@@ -715,7 +720,8 @@ int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
   }
   S.dataflow = mode == 1;
   S.pipe = mode == 2;
-  S.group_waves = mode == 3 ? (chunk ? chunk : kGroupDefaultWaves) : 0;
+  S.group_waves = mode == 3 || mode == 4 ? (chunk ? chunk : kGroupDefaultWaves) : 0;
+  S.group_pairs = mode == 4;
   S.group_spin = kGroupSpinLimit;
   if (const char *e = std::getenv("BDDMP_PASS_SPIN_LIMIT")) S.group_spin = uint32_t(std::strtoul(e, nullptr, 10));
   drop_graph(S);
@@ -723,7 +729,7 @@ int32_t solver_set_launch(Solver &S, int32_t mode, int32_t chunk) {
 }
 
 int32_t solver_get_launch(const Solver &S, int32_t *mode, int32_t *chunk) {
-  if (mode) *mode = S.dataflow ? 1 : (S.pipe ? 2 : (S.group_waves ? 3 : 0));
+  if (mode) *mode = S.dataflow ? 1 : (S.pipe ? 2 : (S.group_waves ? (S.group_pairs ? 4 : 3) : 0));
   if (chunk) *chunk = S.group_waves ? S.group_waves : S.pass[0].chunk;
   return BDDMP_OK;
 }

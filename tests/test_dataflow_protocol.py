@@ -276,6 +276,87 @@ def test_wave_group_launch_runs_every_tile_after_its_dependencies(name, group):
             assert sorted(done_at) == list(range(len(ptr) - 1))
 
 
+def _pair_launch(ptr, lst, beg, w0, nw, slots, rng, done_at, split_rule=True):
+    """One wave-group launch with two tiles per workgroup (launch mode 4): workgroup b takes tiles
+    a = t0 + 2b and a + 1 (if inside the launch), dispatched as in _group_launch. When tile a + 1
+    waits (it lies past the launch's first wave) and its last dependency is a, the workgroup runs a,
+    then a + 1; otherwise both run together once every tile either of them waits for is done
+    (split_rule False: always together). Returns (False on a deadlock, pairs run one after the
+    other)."""
+    t0, t_first, t_end = beg[w0], beg[w0 + 1], beg[w0 + nw]
+    nb = (t_end - t0 + 1) // 2
+    queues = [[b for b in range(nb) if b % 8 == x] for x in range(8)]
+    running = [[] for _ in range(8)]
+    step = {}
+    seq = 0
+
+    def ready(t):
+        return t < t_first or all(u in done_at for u in lst[ptr[t]:ptr[t + 1]])
+
+    def run(t):
+        assert t not in done_at
+        for u in lst[ptr[t]:ptr[t + 1]]:
+            assert u in done_at, f"tile {t} ran before {u}"
+        done_at[t] = len(done_at)
+
+    while any(queues) or any(running):
+        for x in range(8):
+            while queues[x] and len(running[x]) < slots:
+                b = queues[x].pop(0)
+                a = t0 + 2 * b
+                two = a + 1 < t_end
+                d = lst[ptr[a + 1]:ptr[a + 2]] if two else []
+                sequential = split_rule and two and a + 1 >= t_first and len(d) > 0 and d[-1] == a
+                seq += sequential
+                step[b] = [[a], [a + 1]] if sequential else [[a, a + 1] if two else [a]]
+                running[x].append(b)
+        movable = [(x, b) for x in range(8) for b in running[x] if all(ready(t) for t in step[b][0])]
+        if not movable:
+            return False, seq
+        x, b = movable[rng.integers(len(movable))]
+        for t in step[b].pop(0):
+            run(t)
+        if not step[b]:
+            running[x].remove(b)
+    return True, seq
+
+
+@pytest.mark.parametrize("name", ["cfg1", "rand", "batch"])
+@pytest.mark.parametrize("group", [2, 3, 8, 4096])
+def test_two_tile_wave_group_launch_runs_every_tile_after_its_dependencies(name, group):
+    """The two-tile mapping of the wave-group launch (consecutive tiles in pass order per workgroup,
+    a pair across a wave boundary one tile after the other) under per-XCD in-order dispatch with as
+    few as one slot per XCD: every tile runs once, after every tile it reads from, and no launch
+    deadlocks; pairs across a wave boundary do occur."""
+    plan = _plans()[name]()
+    rng = np.random.default_rng(100 + group)
+    n_seq = 0
+    for pass_ in (0, 1):
+        ptr, lst, _ = plan.tile_deps(pass_)
+        beg, _, _ = plan.wave_split(pass_)
+        W = len(beg) - 1
+        for slots in (1, 3):
+            done_at = {}
+            for w0 in range(0, W, group):
+                ok, seq = _pair_launch(ptr, lst, beg, w0, min(group, W - w0), slots, rng, done_at)
+                assert ok, (pass_, w0, slots)
+                n_seq += seq
+            assert sorted(done_at) == list(range(len(ptr) - 1))
+    assert n_seq > 0
+
+
+def test_two_tile_control_pair_run_together_deadlocks():
+    """Control: a pair whose second tile reads from its first, waiting for both tiles' dependencies
+    before running either, waits for itself; the one-after-the-other rule runs it."""
+    # two waves of one tile each: tile 1 depends on tile 0, both in one workgroup
+    ptr, lst, beg = np.array([0, 0, 1]), np.array([0]), np.array([0, 1, 2])
+    ok, _ = _pair_launch(ptr, lst, beg, 0, 2, 1, np.random.default_rng(0), {}, split_rule=False)
+    assert not ok
+    done_at = {}
+    ok, seq = _pair_launch(ptr, lst, beg, 0, 2, 1, np.random.default_rng(0), done_at)
+    assert ok and seq == 1 and done_at == {0: 0, 1: 1}
+
+
 def test_wave_group_control_reversed_waves_deadlock():
     """Control: a launch whose later wave sits in lower blocks than the wave it depends on (the
     order the mapping forbids) deadlocks with one slot per XCD."""

@@ -106,7 +106,7 @@ def test_dataflow_full_size_mrf_bitwise():
 
 def test_dataflow_launch_arguments():
     s = B.Solver(B.Plan(B.Problem.from_ilp(I.config(1))))
-    for bad in ((4, 0), (-1, 0), (1, -1), (1, 5000)):
+    for bad in ((5, 0), (-1, 0), (1, -1), (1, 5000)):
         with pytest.raises(B.BddmpError) as e:
             s.set_launch(*bad)
         assert e.value.code == -1
@@ -118,7 +118,7 @@ def test_dataflow_launch_arguments():
     rows = [([0, k], [1, 1], 1, 1) for k in range(1, 301)]
     big = B.Solver(B.Plan(B.Problem.from_ilp(I.from_rows(301, np.ones(301), rows))))
     assert big.plan.stats.dataflow == 0
-    for mode in (1, 2, 3):
+    for mode in (1, 2, 3, 4):
         with pytest.raises(B.BddmpError) as e:
             big.set_launch(mode, 0)
         assert e.value.code == -1

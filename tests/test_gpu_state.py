@@ -178,8 +178,8 @@ def test_full_size_mrf_workload():
     against the oracle, then the whole 500-iteration run checked by properties (monotone bound
     within float rounding, dual feasibility, finiteness), its bound trajectory against the oracle's
     stored one and its end state against the oracle's stored sample; the same 500 iterations with
-    every wave of a pass in one wave-group launch (the launch form the benchmark picks on this
-    workload) reach bitwise the same end state."""
+    every wave of a pass in one wave-group launch, one and two tiles per workgroup (the launch
+    forms the benchmark chooses from on this workload), reach bitwise the same end state."""
     import torch
 
     ilp = I.config(2)
@@ -230,13 +230,15 @@ def test_full_size_mrf_workload():
     assert_incidence_close(lam[idx], ref["lam"], ref["scale"], what="lambda after 500 iterations (sampled)")
     assert_incidence_close(m0.cpu().numpy().astype(np.float64)[idx], ref["m0"], ref["scale"], what="m0 after 500 (sampled)")
     assert_incidence_close(m1.cpu().numpy().astype(np.float64)[idx], ref["m1"], ref["scale"], what="m1 after 500 (sampled)")
-    print("[cfg2] 500 iterations with wave-group launches", flush=True)
-    g = B.Solver(plan)
-    g.set_launch(3, 4096)
-    g.iterate(500)
-    assert np.array_equal(g.get_lambda().cpu().numpy(), s.get_lambda().cpu().numpy())
-    assert np.array_equal(g.lb_history(1024), hist)
-    torch.cuda.synchronize()
+    for mode in (3, 4):
+        print(f"[cfg2] 500 iterations with wave-group launches (mode {mode})", flush=True)
+        g = B.Solver(plan)
+        g.set_launch(mode, 4096)
+        g.iterate(500)
+        assert np.array_equal(g.get_lambda().cpu().numpy(), s.get_lambda().cpu().numpy())
+        assert np.array_equal(g.lb_history(1024), hist)
+        del g
+        torch.cuda.synchronize()
 
 
 def test_iterate_until_stop_rule():

@@ -71,8 +71,12 @@ struct Layer {
     else f = msg_ld2<false>(D.mf + 2 * L);
   }
   __device__ __forceinline__ void begin_pass(const Dev &D) {
-    if (DIR == kFwd) f = msg_ld2<COH>(D.mf + 2 * L);
-    else b = msg_ld2<COH>(D.mbc + 2 * L);
+    take_pass(msg_ld2<COH>((DIR == kFwd ? D.mf : D.mbc) + 2 * L));
+  }
+  // the same with the pair already loaded
+  __device__ __forceinline__ void take_pass(float2 pair) {
+    if (DIR == kFwd) f = pair;
+    else b = pair;
     m0 = INFINITY;
     m1 = INFINITY;
     if (narrow()) narrow_marginals(lam0);
@@ -413,6 +417,7 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
 
   bool gen = false;
   int ngen = 0, myk = 0, G = 1, TW = 0, TC = 0;
+  float2 pass_pair = make_float2(0.0f, 0.0f);
   uint32_t ar[NARROW_ONLY ? 1 : kFlatR];
   float fr[NARROW_ONLY ? 1 : kFlatR];
   int kr[NARROW_ONLY ? 1 : kFlatR];
@@ -475,12 +480,17 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
     __syncthreads();
     if constexpr (kDeferred) {
       wait();
-      if (active) ly.begin_pass(D);
+      // the pair of messages this pass writes, for every lane (a lane past the tile's layers reads
+      // the first position's pair), issued before the node staging's loads and used after them: a
+      // narrow layer's min-marginals are taken once the general layers' are
+      pass_pair = msg_ld2<COH>((DIR == kFwd ? D.mf : D.mbc) + 2 * (active ? ly.L : p0));
     }
     if (flat) {
       // own nodes: arcs and forward messages; child nodes: backward messages into LDS. Node
-      // t = s + r * kTile, its layer's rank from the node maps in the stage; slots past the tile's
-      // nodes are skipped per wavefront.
+      // t = s + r * kTile, its layer's rank from the node maps in the stage. Every lane issues
+      // every load (a slot past the tile's nodes reads slot 2 p0, which exists in every slot
+      // array, and is marked unused): with a branch per slot the compiler waited for one slot's
+      // loads before issuing the next slot's.
       const uint8_t *maps = reinterpret_cast<const uint8_t *>(s_cb);
       int ks[kFlatR], kcs[kFlatR];
 #pragma unroll
@@ -491,16 +501,15 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
       }
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
-        kr[r] = -1;
         const int t = s + r * kTile;
-        if (r * kTile < TW && t < TW) {
-          const int k = ks[r];
-          const int u = t - T.wo[k];
-          kr[r] = k;
-          ur[r] = u;
-          ar[r] = D.garcs[T.os[k] + u];
-          fr[r] = msg_ld<COH && DIR == kFwd>(D.mf + T.os[k] + u);
-        }
+        const bool ok = r * kTile < TW && t < TW;
+        const int k = ks[r];
+        const int u = ok ? t - T.wo[k] : 0;
+        const int q = ok ? T.os[k] + u : 2 * p0;
+        kr[r] = ok ? k : -1;
+        ur[r] = u;
+        ar[r] = D.garcs[q];
+        fr[r] = msg_ld<COH && DIR == kFwd>(D.mf + q);
       }
       // all loads of the lane first, then the LDS stores: a store right after its load would wait
       // for that load before the next one issues
@@ -508,15 +517,18 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r) {
         const int t = s + r * kTile;
-        kc[r] = -1;
+        const bool ok = r * kTile < TC && t < TC;
+        const int k = kcs[r];
+        kc[r] = ok ? k : -1;
+        cbr[r] = msg_ld<COH && DIR == kBwd>(D.mbc + (ok ? T.cs[k] + (t - T.co[k]) : 2 * p0));
+      }
+      // the packed in-arcs (no slot of that array exists in every plan, so these stay conditional
+      // and go last)
+#pragma unroll
+      for (int r = 0; r < kFlatR; ++r) {
         pkc[r] = kManyInArcs;
-        cbr[r] = 0.0f;
-        if (r * kTile < TC && t < TC) {
-          const int k = kcs[r];
-          kc[r] = k;
-          cbr[r] = msg_ld<COH && DIR == kBwd>(D.mbc + T.cs[k] + (t - T.co[k]));
-          if (DIR == kFwd && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (t - T.co[k])];
-        }
+        const int k = kc[r];
+        if (DIR == kFwd && k >= 0 && T.osc[k] >= 0) pkc[r] = D.rin[T.rb[k] + (s + r * kTile - T.co[k])];
       }
       // every lane has read its ranks before the stage takes the backward messages
       __syncthreads();
@@ -563,6 +575,8 @@ __device__ __forceinline__ void wave_tile(const Dev &D, WaveLds<NARROW_ONLY> &sh
       ly.m0 = float_of(T.m0[myk]);
       ly.m1 = float_of(T.m1[myk]);
     }
+    if constexpr (kDeferred)
+      if (active && !gen) ly.take_pass(pass_pair);
     if (DIR == kFwd && flat) {
 #pragma unroll
       for (int r = 0; r < kFlatR; ++r)

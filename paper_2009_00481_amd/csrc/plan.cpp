@@ -16,6 +16,9 @@
 // therefore one contiguous segment, and each wave is one contiguous layer range. Node arrays
 // follow the layer order. Arcs are packed as two 16-bit child codes per node.
 #include <algorithm>
+#include <mutex>
+#include <exception>
+#include <thread>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -98,6 +101,39 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// f(begin, end) over [0, n) in contiguous chunks on up to 16 host threads (one for small n); an
+// exception thrown in any chunk is rethrown here once every chunk has ended
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+  constexpr int64_t kMinChunk = int64_t(1) << 16;
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int64_t nt = std::min<int64_t>({int64_t(hw ? hw : 1), 16, (n + kMinChunk - 1) / kMinChunk});
+  if (nt <= 1) {
+    if (n > 0) f(int64_t(0), n);
+    return;
+  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::exception_ptr> err(static_cast<size_t>(nt));
+  auto run = [&](int64_t k) {
+    try {
+      if (k * chunk < n) f(k * chunk, std::min(n, (k + 1) * chunk));
+    } catch (...) {
+      err[size_t(k)] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  int64_t k = 1;
+  try {
+    for (; k < nt; ++k) th.emplace_back(run, k);
+  } catch (...) {
+    for (; k < nt; ++k) run(k);  // no more threads: the remaining chunks here
+  }
+  run(0);
+  for (auto &t : th) t.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
+}
+
 // Greedy tiling of a pass: consecutive variables share a tile while their layers fit kTile, their
 // general levels hold at most cap nodes (wwork: per variable) and they belong to the same group of
 // instances (grp); a variable with more rows than kTile gets a big tile of its own. Tiles are
@@ -148,7 +184,8 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
   if (int64_t(P.meta.size()) != I || int64_t(P.child.size()) != I || int64_t(P.parent.size()) != I ||
       int64_t(P.garcs.size()) != S)
     return "array sizes";
-  for (int64_t L = 0; L < I; ++L) {
+  // one layer's checks (seen0 / seen1: its arcs met in the in-arc lists), nullptr when sound
+  auto check_layer = [&](int64_t L, std::vector<int32_t> &seen0, std::vector<int32_t> &seen1) -> const char * {
     const int64_t os = P.own_slot[L];
     const int32_t w = ownw[L], wc = childw[L];
     if (w <= 0 || w > kMaxWidth || os < 0 || os + w > S) return "own slots";
@@ -198,7 +235,8 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
       if (wc > 0 && !exit_cut[L]) {
         const int64_t rb = g[3];
         if (rb < 0 || rb + wc >= int64_t(P.rbeg.size())) return "in-arc base";
-        std::vector<int32_t> seen0(size_t(w), 0), seen1(size_t(w), 0);
+        seen0.assign(size_t(w), 0);
+        seen1.assign(size_t(w), 0);
         int64_t cnt = 0;
         if (P.rin.size() != P.rbeg.size()) return "packed in-arcs";
         for (int32_t v = 0; v < wc; ++v) {
@@ -237,6 +275,26 @@ std::string validate_layout(const Plan &P, const std::vector<int32_t> &ownw, con
     const int32_t nj = P.var_nj[P.layer_var[L]];
     if (len == 0 || pos >= len || int32_t(len) != std::min<int32_t>(nj, int32_t(kMetaField))) return "segment";
     if (P.layer_of[P.canon_of[L]] != L) return "canon_of / layer_of";
+    return nullptr;
+  };
+  // the layers on several threads; the first failing layer's message
+  {
+    std::mutex mu;
+    int64_t bad_at = I;
+    const char *bad = nullptr;
+    parallel_for(I, [&](int64_t L0, int64_t L1) {
+      std::vector<int32_t> seen0, seen1;
+      for (int64_t L = L0; L < L1; ++L)
+        if (const char *e = check_layer(L, seen0, seen1)) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (L < bad_at) {
+            bad_at = L;
+            bad = e;
+          }
+          return;
+        }
+    });
+    if (bad) return bad;
   }
   // every layer is visited exactly once per pass; a normal tile holds whole segments of variables
   // with at most kTile rows, a big tile exactly one variable
@@ -851,36 +909,46 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
     P.child[Lq] = child_layer[Lq];
     if (child_layer[Lq] >= 0) P.parent[child_layer[Lq]] = int32_t(Lq);
   }
-  P.n_general = 0;
-  for (int64_t Lq = 0; Lq < I; ++Lq) {
-    const int32_t c = P.canon_of[Lq];
-    const int32_t j = inc_row[c];
-    const Shape &sh = P.shapes[P.row_shape[j]];
-    const int32_t l = level[Lq];
-    const bool narrow = ownw[Lq] <= 2 && childw[Lq] <= 2;
-    uint32_t meta = 0;
-    // child of arc (u, beta): a node of the next level, or at a cut the arc's own virtual slot
-    auto arc_child = [&](int32_t u, int beta) -> int32_t {
-      const int32_t ch = beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u];
-      return (exit_cut[Lq] && ch >= 0) ? 2 * u + beta : ch;
-    };
-    for (int32_t u = 0; u < ownw[Lq]; ++u)
-      P.garcs[size_t(P.own_slot[Lq] + u)] = code16(arc_child(u, 0)) | (code16(arc_child(u, 1)) << 16);
-    if (narrow) {
-      for (int32_t u = 0; u < 2; ++u) {
-        const uint32_t lo = u < ownw[Lq] ? code2(arc_child(u, 0)) : kC2Bot;
-        const uint32_t hi = u < ownw[Lq] ? code2(arc_child(u, 1)) : kC2Bot;
-        meta |= (lo | (hi << 2)) << (4 * u);
+  // each layer writes only its own arcs and meta word: on several threads, general layers counted
+  // per chunk
+  std::vector<int64_t> n_gen_chunk;
+  std::mutex n_gen_mu;
+  parallel_for(I, [&](int64_t L0, int64_t L1) {
+    int64_t n_gen = 0;
+    for (int64_t Lq = L0; Lq < L1; ++Lq) {
+      const int32_t c = P.canon_of[Lq];
+      const int32_t j = inc_row[c];
+      const Shape &sh = P.shapes[P.row_shape[j]];
+      const int32_t l = level[Lq];
+      const bool narrow = ownw[Lq] <= 2 && childw[Lq] <= 2;
+      uint32_t meta = 0;
+      // child of arc (u, beta): a node of the next level, or at a cut the arc's own virtual slot
+      auto arc_child = [&](int32_t u, int beta) -> int32_t {
+        const int32_t ch = beta ? sh.hi[sh.first[l] + u] : sh.lo[sh.first[l] + u];
+        return (exit_cut[Lq] && ch >= 0) ? 2 * u + beta : ch;
+      };
+      for (int32_t u = 0; u < ownw[Lq]; ++u)
+        P.garcs[size_t(P.own_slot[Lq] + u)] = code16(arc_child(u, 0)) | (code16(arc_child(u, 1)) << 16);
+      if (narrow) {
+        for (int32_t u = 0; u < 2; ++u) {
+          const uint32_t lo = u < ownw[Lq] ? code2(arc_child(u, 0)) : kC2Bot;
+          const uint32_t hi = u < ownw[Lq] ? code2(arc_child(u, 1)) : kC2Bot;
+          meta |= (lo | (hi << 2)) << (4 * u);
+        }
+        meta |= uint32_t(ownw[Lq]) << kMetaWidthShift;
+      } else {
+        ++n_gen;
       }
-      meta |= uint32_t(ownw[Lq]) << kMetaWidthShift;
-    } else {
-      ++P.n_general;
+      if (l == 0) meta |= kMetaRootBit;
+      const uint32_t len = uint32_t(std::min<int32_t>(P.var_nj[P.layer_var[Lq]], int32_t(kMetaField)));
+      meta |= (std::min<uint32_t>(segpos[Lq], kMetaField) << kMetaPosShift) | (len << kMetaLenShift);
+      P.meta[Lq] = meta;
     }
-    if (l == 0) meta |= kMetaRootBit;
-    const uint32_t len = uint32_t(std::min<int32_t>(P.var_nj[P.layer_var[Lq]], int32_t(kMetaField)));
-    meta |= (std::min<uint32_t>(segpos[Lq], kMetaField) << kMetaPosShift) | (len << kMetaLenShift);
-    P.meta[Lq] = meta;
-  }
+    std::lock_guard<std::mutex> lk(n_gen_mu);
+    n_gen_chunk.push_back(n_gen);
+  });
+  P.n_general = 0;
+  for (int64_t v : n_gen_chunk) P.n_general += v;
   if (P.n_general) {
     // general records for every layer (a general level's neighbours read them too), and for each
     // general layer with a child level the in-arc lists of that child level: the pull form of the
@@ -891,7 +959,20 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       if (P.child[Lq] >= 0) P.gnb[2 * size_t(Lq)] = int32_t(P.own_slot[P.child[Lq]]);
       if (P.parent[Lq] >= 0) P.gnb[2 * size_t(Lq) + 1] = int32_t(P.cslot[P.parent[Lq]]);
     }
-    std::vector<std::vector<uint16_t>> lists;
+    // per child node its in-arcs in ascending source order (the 0-arc before the 1-arc of one
+    // source), by a counting sort into the flat arrays (sized beforehand)
+    {
+      size_t nb = 0, na = 0;
+      for (int64_t Lq = 0; Lq < I; ++Lq)
+        if (((P.meta[Lq] >> kMetaWidthShift) & 3u) == 0u && childw[Lq] > 0 && !exit_cut[Lq]) {
+          nb += size_t(childw[Lq]) + 1;
+          na += 2 * size_t(ownw[Lq]);
+        }
+      P.rbeg.reserve(nb);
+      P.rin.reserve(nb);
+      P.rarc.reserve(na);
+    }
+    std::vector<int64_t> at;
     for (int64_t Lq = 0; Lq < I; ++Lq) {
       int32_t *g = &P.grec[4 * size_t(Lq)];
       g[0] = int32_t(P.own_slot[Lq]);
@@ -901,19 +982,28 @@ int32_t make_plan(const Problem &p, const bddmp_options &opt, Plan &P) {
       const bool narrow = ((P.meta[Lq] >> kMetaWidthShift) & 3u) != 0u;
       if (narrow || childw[Lq] == 0 || exit_cut[Lq]) continue;
       g[3] = int32_t(P.rbeg.size());
-      lists.assign(size_t(childw[Lq]), {});
+      const int32_t wc = childw[Lq];
+      const uint32_t *arcs = &P.garcs[size_t(P.own_slot[Lq])];
+      at.assign(size_t(wc) + 1, 0);
       for (int32_t u = 0; u < ownw[Lq]; ++u) {
-        const uint32_t a = P.garcs[size_t(P.own_slot[Lq] + u)];
-        if ((a & 0xFFFFu) < kTop) lists[a & 0xFFFFu].push_back(uint16_t(u));
-        if ((a >> 16) < kTop) lists[a >> 16].push_back(uint16_t(uint32_t(u) | kInArcHi));
+        if ((arcs[u] & 0xFFFFu) < kTop) ++at[(arcs[u] & 0xFFFFu) + 1];
+        if ((arcs[u] >> 16) < kTop) ++at[(arcs[u] >> 16) + 1];
       }
-      for (const auto &li : lists) {
-        P.rbeg.push_back(int32_t(P.rarc.size()));
-        P.rarc.insert(P.rarc.end(), li.begin(), li.end());
-        P.rin.push_back(li.size() > 2 ? kManyInArcs
-                                      : (li.size() > 0 ? li[0] : kNoArc16) | ((li.size() > 1 ? li[1] : kNoArc16) << 16));
+      const int64_t base = int64_t(P.rarc.size());
+      for (int32_t v = 0; v < wc; ++v) at[size_t(v) + 1] += at[size_t(v)];
+      for (int32_t v = 0; v <= wc; ++v) P.rbeg.push_back(int32_t(base + at[size_t(v)]));
+      P.rarc.resize(size_t(base + at[size_t(wc)]));
+      for (int32_t u = 0; u < ownw[Lq]; ++u) {
+        if ((arcs[u] & 0xFFFFu) < kTop) P.rarc[size_t(base + at[arcs[u] & 0xFFFFu]++)] = uint16_t(u);
+        if ((arcs[u] >> 16) < kTop) P.rarc[size_t(base + at[arcs[u] >> 16]++)] = uint16_t(uint32_t(u) | kInArcHi);
       }
-      P.rbeg.push_back(int32_t(P.rarc.size()));
+      // at[v] is now the end of v's list, rbeg (just appended) its start
+      const int32_t *beg = &P.rbeg[P.rbeg.size() - size_t(wc) - 1];
+      for (int32_t v = 0; v < wc; ++v) {
+        const int64_t b0 = beg[v], k = int64_t(beg[v + 1]) - b0;
+        P.rin.push_back(k > 2 ? kManyInArcs
+                              : (k > 0 ? P.rarc[size_t(b0)] : kNoArc16) | ((k > 1 ? P.rarc[size_t(b0) + 1] : kNoArc16) << 16));
+      }
       P.rin.push_back(kManyInArcs);
       if (P.rarc.size() >= size_t(INT32_MAX)) return set_error(BDDMP_BDD_TOO_LARGE, "too many in-arcs");
     }

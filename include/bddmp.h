@@ -257,6 +257,14 @@ int32_t bddmp_plan_export_tile_deps(const bddmp_plan *plan, int32_t pass, int32_
 int32_t bddmp_plan_export_wave_split(const bddmp_plan *plan, int32_t pass, int32_t *tile_begin, int32_t *mid,
                                      int32_t *b_wait);
 
+/*
+ * A 64-bit digest (FNV-1a) of every array the plan holds for the device and of its layout sizes,
+ * for reproducibility checks: plans that upload the same bytes have the same digest, and the same
+ * problem and options give the same plan whatever the number of host threads that built it.
+ * digest: host uint64 out. INVALID_ARG for a null plan or digest.
+ */
+int32_t bddmp_plan_digest(const bddmp_plan *plan, uint64_t *digest);
+
 /* Forward and backward wave of every variable (1-based, 0 for variables in no row); host [n_vars]. */
 int32_t bddmp_plan_export_waves(const bddmp_plan *plan, int32_t *wave_fwd, int32_t *wave_bwd);
 

@@ -81,6 +81,7 @@ SIGNATURES = {
     "bddmp_plan_export_order": (_I32, [_P, _P]),
     "bddmp_plan_export_structure": (_I32, [_P, _P, _P, _P, _P]),
     "bddmp_plan_export_waves": (_I32, [_P, _P, _P]),
+    "bddmp_plan_digest": (_I32, [_P, _P]),
     "bddmp_plan_export_tile_deps": (_I32, [_P, _I32, _P, _P, _P]),
     "bddmp_plan_export_wave_split": (_I32, [_P, _I32, _P, _P, _P]),
     "bddmp_solver_bind": (_I32, [_P, _P, C.c_size_t, _P, C.POINTER(_P)]),
@@ -276,6 +277,12 @@ def bddmp_plan_export_waves(plan, n: int):
     b = np.zeros(max(n, 1), np.int32)
     _check(lib().bddmp_plan_export_waves(plan, _ptr(f), _ptr(b)))
     return f[:n], b[:n]
+
+
+def bddmp_plan_digest(plan) -> int:
+    d = np.zeros(1, np.uint64)
+    _check(lib().bddmp_plan_digest(plan, _ptr(d)))
+    return int(d[0])
 
 
 def bddmp_plan_export_tile_deps(plan, pass_: int, n_tiles: int, n_deps: int):
@@ -504,6 +511,10 @@ class Plan:
 
     def waves(self):
         return bddmp_plan_export_waves(self.h, self.n)
+
+    def digest(self) -> int:
+        """64-bit digest of every array the plan uploads and of its layout sizes."""
+        return bddmp_plan_digest(self.h)
 
     def tile_deps(self, pass_: int):
         """(dep_ptr, dep_list, tile_group) of the dataflow launch's tiles in pass 0 (forward) or 1 (backward)."""

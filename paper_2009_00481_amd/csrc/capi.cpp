@@ -48,6 +48,15 @@ int32_t guarded(F &&f) {
   }
 }
 
+// FNV-1a over the bytes of one array, then its byte count
+template <class V>
+void digest_add(uint64_t &h, const V &v) {
+  const unsigned char *b = reinterpret_cast<const unsigned char *>(v.data());
+  const size_t nb = v.size() * sizeof(v[0]);
+  for (size_t i = 0; i < nb; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  for (int k = 0; k < 8; ++k) h = (h ^ ((uint64_t(nb) >> (8 * k)) & 0xFFu)) * 1099511628211ull;
+}
+
 }  // namespace
 
 extern "C" {
@@ -345,6 +354,30 @@ int32_t bddmp_plan_export_wave_split(const bddmp_plan *h, int32_t pass, int32_t 
     if (b_wait) b_wait[w] = split[w].b_wait;
   }
   if (tile_begin) tile_begin[waves.size()] = waves.empty() ? 0 : waves.back().tile_end;
+  return BDDMP_OK;
+}
+
+int32_t bddmp_plan_digest(const bddmp_plan *h, uint64_t *digest) {
+  if (!h || !digest) return set_error(BDDMP_INVALID_ARG, "null plan or digest");
+  const bddmp::Plan &P = h->plan;
+  uint64_t d = 1469598103934665603ull;
+  const std::vector<int64_t> sizes{P.n, P.m, P.N, P.I, P.S, P.Sc, P.Df, P.Db, P.n_general, int64_t(P.lay.total)};
+  digest_add(d, sizes);
+  digest_add(d, P.meta); digest_add(d, P.child); digest_add(d, P.parent); digest_add(d, P.garcs);
+  digest_add(d, P.grec); digest_add(d, P.gnb); digest_add(d, P.rbeg); digest_add(d, P.rin); digest_add(d, P.rarc);
+  digest_add(d, P.canon_of); digest_add(d, P.layer_of); digest_add(d, P.layer_var); digest_add(d, P.root_slot);
+  digest_add(d, P.fwd_tiles); digest_add(d, P.bwd_tiles); digest_add(d, P.fwd_big); digest_add(d, P.bwd_big);
+  digest_add(d, P.bwd_list); digest_add(d, P.bdd_canon_off); digest_add(d, P.var_first); digest_add(d, P.var_nj);
+  digest_add(d, P.own_slot); digest_add(d, P.cslot); digest_add(d, P.cuts); digest_add(d, P.cut_slots);
+  digest_add(d, P.cut_live); digest_add(d, P.cut_rb); digest_add(d, P.cut_arc); digest_add(d, P.inst_cut);
+  digest_add(d, P.inst_cut_idx); digest_add(d, P.exit_rec); digest_add(d, P.fdep_ptr); digest_add(d, P.fdep_list);
+  digest_add(d, P.bdep_ptr); digest_add(d, P.bdep_list); digest_add(d, P.ftinfo); digest_add(d, P.btinfo);
+  digest_add(d, P.ftrec); digest_add(d, P.btrec); digest_add(d, P.fqptr); digest_add(d, P.fqtile);
+  digest_add(d, P.bqptr); digest_add(d, P.bqtile); digest_add(d, P.fgt); digest_add(d, P.bgt); digest_add(d, P.fgm);
+  digest_add(d, P.bgm); digest_add(d, P.wave_f); digest_add(d, P.wave_b); digest_add(d, P.order); digest_add(d, P.rank);
+  digest_add(d, P.cost); digest_add(d, P.inc_var); digest_add(d, P.var_group); digest_add(d, P.inst_row32);
+  digest_add(d, P.inst_lb_const);
+  *digest = d;
   return BDDMP_OK;
 }
 

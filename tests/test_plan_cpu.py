@@ -249,3 +249,24 @@ def test_empty_and_degenerate_plans():
     # zero coefficients are dropped from I_j
     pl = _plan(I.from_rows(3, np.zeros(3), [([0, 1, 2], [1, 0, 1], 0, 1)]))
     assert pl.stats.n_incidences == 2
+
+
+def test_plan_digest_is_reproducible():
+    """The planner fills the layers' arcs and meta words and checks the layout on several host
+    threads over layer ranges; the same problems and options must give the same plan bytes on every
+    build (a batch with general levels, large enough for several threads), other options other
+    bytes."""
+    probs = [B.Problem.from_ilp(q) for q in I.batch_config(4, p_range=(40, 64), d_range=(200, 600))]
+    plan = B.Plan(probs, wave_align=1)
+    assert plan.stats.n_incidences > 4 * 65536 and plan.stats.max_width > 2
+    d = plan.digest()
+    for _ in range(3):
+        assert B.Plan(probs, wave_align=1).digest() == d
+    assert B.Plan(probs, wave_align=0).digest() != d
+    assert B.Plan(probs[:3], wave_align=1).digest() != d
+
+
+def test_plan_digest_arguments():
+    with pytest.raises(B.BddmpError) as e:
+        B._check(B.lib().bddmp_plan_digest(None, None))
+    assert e.value.code == -1
